@@ -1,0 +1,260 @@
+"""CPU oracle of the geometry-embedding hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this package.  It shares no code with the GPU
+library: the C sources here (exact.c, embed.c) are compiled on their own into
+liboracle.so and evaluate the plain definitions with exact predicates.
+
+What each function follows (section names of the paper):
+  classify_blocks / solid_points  -- a cell is solid iff its centre lies in the
+      closed solid bounded by the mesh ("Solid Voxelization Approaches":
+      ray-cast parity; "Partial Surface Voxelization").  Points on the surface
+      are solid; the +x ray is symbolically perturbed (simulation of
+      simplicity) so parity never depends on rays grazing edges or vertices.
+  refine -- "Refinement Flagging and Propagation": solid-boundary blocks,
+      solid-adjacent blocks, N_prop propagation passes (Eq. 3), 2:1 eligibility.
+  links -- "Boundary Cell Identification" and "Link-Length Computation": a
+      fluid cell with a solid lattice neighbour has a cut link whose length q is
+      the nearest surface crossing along the link, as a fraction of the link.
+  grad -- derivative of q with respect to the hit triangle's vertices
+      (closed form; not in the paper).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from fractions import Fraction
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "liboracle.so")
+_SRC = [os.path.join(_HERE, f) for f in ("exact.c", "embed.c")]
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2 -fopenmp)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+               "-Wno-unused-variable", "-Wno-maybe-uninitialized", *_SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        i64, i32, dbl = C.c_int64, C.c_int, C.c_double
+        L.or_orient2d.argtypes = [dbl] * 6
+        L.or_orient2d_exact.argtypes = [dbl] * 6
+        L.or_orient3d.argtypes = [P] * 4
+        L.or_orient3d_exact.argtypes = [P] * 4
+        L.or_orient3d_value.argtypes = [P] * 4
+        L.or_orient3d_value.restype = dbl
+        L.or_solid_points_brute.argtypes = [P, P, i32, i64, P, P]
+        L.or_solid_points.argtypes = [P, P, i32, P, i64, P, P]
+        L.or_classify_blocks.argtypes = [P, P, i32, P, i32, i64, P, i32, P]
+        L.or_refine.argtypes = [P, i32, i64, P, P, i32, P, P, P, P]
+        L.or_refine.restype = i64
+        L.or_links.argtypes = [P, P, i32, P, i32, i64, P, i32, i64, P, P, P, P, P, P]
+        L.or_links.restype = i64
+        L.or_q_points.argtypes = [P, P, i32, P, i32, i64, P, P, P, P, P]
+        L.or_grad.argtypes = [P, P, i32, P, i32, i64, P, i64, P, P, P, P, P]
+        L.or_num_threads.restype = i32
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _mesh_arrays(mesh):
+    V = np.ascontiguousarray(mesh.verts, dtype=np.float64)  # float32 -> float64 is exact
+    T = np.ascontiguousarray(mesh.tris, dtype=np.int32)
+    return V, T
+
+
+def orient2d(a, b, c) -> int:
+    return lib().or_orient2d(float(a[0]), float(a[1]), float(b[0]), float(b[1]),
+                             float(c[0]), float(c[1]))
+
+
+def orient3d(a, b, c, d, exact_only: bool = False) -> int:
+    arr = [np.ascontiguousarray(x, dtype=np.float64) for x in (a, b, c, d)]
+    f = lib().or_orient3d_exact if exact_only else lib().or_orient3d
+    return f(*[_p(x) for x in arr])
+
+
+def num_threads() -> int:
+    return lib().or_num_threads()
+
+
+# ----------------------------------------------------------------------------
+# grid helpers
+# ----------------------------------------------------------------------------
+
+def level0_blocks(n0) -> np.ndarray:
+    """All level-0 blocks, bx fastest."""
+    nb = [n // 4 for n in n0]
+    z, y, x = np.meshgrid(np.arange(nb[2]), np.arange(nb[1]), np.arange(nb[0]), indexing="ij")
+    return np.stack([x.ravel(), y.ravel(), z.ravel()], 1).astype(np.int32)
+
+
+def n_prop(d_spec: float) -> int:
+    """Eq. 3 with the block length 4*dx_L: the 1/2^L factor cancels, leaving
+    N_prop = 1 + floor(d_spec / (4 sqrt(2))) in base-cell units; the floor is
+    taken exactly (largest k with 32 k^2 <= d_spec^2)."""
+    d = Fraction(d_spec)
+    if d <= 0:
+        return 1
+    k = int(float(d) / (4 * 2 ** 0.5))
+    while 32 * (k + 1) ** 2 <= d * d:
+        k += 1
+    while k > 0 and 32 * k ** 2 > d * d:
+        k -= 1
+    return 1 + k
+
+
+def cell_centres(bcoord: np.ndarray, L: int) -> np.ndarray:
+    """[nb, 64, 3] cell centres, t = I + 4J + 16K."""
+    t = np.arange(64)
+    I = np.stack([t & 3, (t >> 2) & 3, t >> 4], 1)
+    cells = 4 * bcoord[:, None, :].astype(np.int64) + I[None]
+    return (cells + 0.5) * 2.0 ** (-L)
+
+
+# ----------------------------------------------------------------------------
+# classification
+# ----------------------------------------------------------------------------
+
+def solid_points(mesh, n0, pts: np.ndarray, brute: bool = False) -> np.ndarray:
+    V, T = _mesh_arrays(mesh)
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros(len(pts), dtype=np.uint8)
+    n0a = np.ascontiguousarray(n0, dtype=np.int32)
+    if brute:
+        lib().or_solid_points_brute(_p(V), _p(T), T.shape[0], len(pts), _p(pts), _p(out))
+    else:
+        lib().or_solid_points(_p(V), _p(T), T.shape[0], _p(n0a), len(pts), _p(pts), _p(out))
+    return out
+
+
+def classify_blocks(mesh, n0, L: int, bcoord: np.ndarray, halo: bool = False) -> np.ndarray:
+    V, T = _mesh_arrays(mesh)
+    bc = np.ascontiguousarray(bcoord, dtype=np.int32)
+    w = 216 if halo else 64
+    out = np.zeros((len(bc), w), dtype=np.uint8)
+    n0a = np.ascontiguousarray(n0, dtype=np.int32)
+    lib().or_classify_blocks(_p(V), _p(T), T.shape[0], _p(n0a), L, len(bc), _p(bc),
+                             1 if halo else 0, _p(out))
+    return out
+
+
+def pack_bits(solid_cells: np.ndarray) -> np.ndarray:
+    """[nb, 64] uint8 -> [nb] uint64 with bit t = cell t."""
+    w = (solid_cells.astype(np.uint64) & np.uint64(1)) << np.arange(64, dtype=np.uint64)
+    return np.bitwise_or.reduce(w, axis=1)
+
+
+# ----------------------------------------------------------------------------
+# refinement
+# ----------------------------------------------------------------------------
+
+def refine(n0, L: int, bcoord: np.ndarray, solid_cells: np.ndarray, nprop: int) -> dict:
+    bc = np.ascontiguousarray(bcoord, dtype=np.int32)
+    nb = len(bc)
+    s = np.ascontiguousarray(solid_cells, dtype=np.uint8)
+    bclass = np.zeros(nb, np.uint8)
+    ref = np.zeros(nb, np.uint8)
+    cmap = np.zeros(nb, np.int32)
+    child = np.zeros((8 * nb, 3), np.int32)
+    n0a = np.ascontiguousarray(n0, dtype=np.int32)
+    nch = lib().or_refine(_p(n0a), L, nb, _p(bc), _p(s), int(nprop), _p(bclass), _p(ref),
+                          _p(cmap), _p(child))
+    return {"bclass": bclass, "refine": ref, "child_map": cmap, "children": child[:nch].copy()}
+
+
+# ----------------------------------------------------------------------------
+# links
+# ----------------------------------------------------------------------------
+
+def links(mesh, n0, L: int, bcoord: np.ndarray, lattice: int) -> dict:
+    V, T = _mesh_arrays(mesh)
+    bc = np.ascontiguousarray(bcoord, dtype=np.int32)
+    nb = len(bc)
+    n0a = np.ascontiguousarray(n0, dtype=np.int32)
+    mask = np.zeros(nb * 64, np.uint32)
+    cap = 0
+    args = lambda cap, arrs: [_p(V), _p(T), T.shape[0], _p(n0a), L, nb, _p(bc), lattice, cap,
+                              _p(mask)] + [_p(a) for a in arrs]
+    arrs = [np.zeros(1, np.int32), np.zeros(1, np.uint8), np.zeros(1, np.float64),
+            np.zeros(1, np.int32), np.zeros(1, np.uint8)]
+    n = lib().or_links(*args(0, arrs))
+    arrs = [np.zeros(max(n, 1), np.int32), np.zeros(max(n, 1), np.uint8),
+            np.zeros(max(n, 1), np.float64), np.zeros(max(n, 1), np.int32),
+            np.zeros(max(n, 1), np.uint8)]
+    n2 = lib().or_links(*args(n, arrs))
+    assert n2 == n
+    return {"mask": mask.reshape(nb, 64), "n": int(n), "cell": arrs[0][:n], "dir": arrs[1][:n],
+            "q": arrs[2][:n], "tri": arrs[3][:n], "tied": arrs[4][:n]}
+
+
+def q_points(mesh, n0, L: int, cells: np.ndarray, dirs: np.ndarray) -> dict:
+    V, T = _mesh_arrays(mesh)
+    cells = np.ascontiguousarray(cells, dtype=np.int32).reshape(-1, 3)
+    dirs = np.ascontiguousarray(dirs, dtype=np.uint8)
+    n = len(cells)
+    q = np.zeros(n, np.float64)
+    tri = np.zeros(n, np.int32)
+    tied = np.zeros(n, np.uint8)
+    n0a = np.ascontiguousarray(n0, dtype=np.int32)
+    lib().or_q_points(_p(V), _p(T), T.shape[0], _p(n0a), L, n, _p(cells), _p(dirs), _p(q),
+                      _p(tri), _p(tied))
+    return {"q": q, "tri": tri, "tied": tied}
+
+
+def grad(mesh, n0, L: int, bcoord: np.ndarray, link_cell, link_dir, link_tri, w) -> np.ndarray:
+    V, T = _mesh_arrays(mesh)
+    bc = np.ascontiguousarray(bcoord, dtype=np.int32)
+    lc = np.ascontiguousarray(link_cell, dtype=np.int32)
+    ld = np.ascontiguousarray(link_dir, dtype=np.uint8)
+    lt = np.ascontiguousarray(link_tri, dtype=np.int32)
+    ww = np.ascontiguousarray(w, dtype=np.float64)
+    g = np.zeros((V.shape[0], 3), np.float64)
+    n0a = np.ascontiguousarray(n0, dtype=np.int32)
+    lib().or_grad(_p(V), _p(T), V.shape[0], _p(n0a), L, len(bc), _p(bc), len(lc), _p(lc), _p(ld),
+                  _p(lt), _p(ww), _p(g))
+    return g
+
+
+# ----------------------------------------------------------------------------
+# the whole path, level by level
+# ----------------------------------------------------------------------------
+
+def embed(mesh, n0, lf: int, lattice: int, d_spec: float = 2.0, with_links: bool = True) -> dict:
+    """Level-by-level voxelization and refinement (levels 0..lf), then the
+    cut-link table on level lf."""
+    npr = n_prop(d_spec)
+    bcoord = level0_blocks(n0)
+    levels = []
+    for L in range(lf + 1):
+        cells = classify_blocks(mesh, n0, L, bcoord)
+        rec = {"level": L, "bcoord": bcoord, "solid_cells": cells, "solid": pack_bits(cells)}
+        if L < lf:
+            r = refine(n0, L, bcoord, cells, npr)
+            rec.update(r)
+            bcoord = r["children"]
+        levels.append(rec)
+    out = {"levels": levels, "n_prop": npr}
+    if with_links:
+        out["links"] = links(mesh, n0, lf, levels[-1]["bcoord"], lattice)
+    return out
