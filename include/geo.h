@@ -1,0 +1,214 @@
+/*
+ * libgeo: MI355X (gfx950) geometry embedding into a block-structured forest
+ * of octrees -- solid voxelization, near-wall refinement flags, and the
+ * cut-link (q) lookup table for interpolated bounce-back, with the q backward.
+ *
+ * The operations follow the paper "GPU-native Embedding of Complex Geometries
+ * in Adaptive Octree Grids Applied to the Lattice Boltzmann Method"
+ * (Methodology: Spatial Binning; Voxelization and Near-Wall Refinement;
+ * Boundary Cell Identification; Memory Allocations for Boundary Cells;
+ * Link-Length Computation; Eq. 2 and Eq. 3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Units: base-cell units; the domain is [0,n0x] x [0,n0y] x [0,n0z].  Level
+ *    L has cells of size h = 2^-L, centres at (i + 1/2) h, and blocks of 4^3
+ *    cells.  A block coordinate b (level-L block units) covers cells 4b..4b+3.
+ *    Cell t of a block is t = I + 4 J + 16 K (the paper's LINEAR(I, 4)).
+ *  - Lattice directions: k = (cx+1) + 3 (cy+1) + 9 (cz+1), k = 13 is the rest
+ *    direction; D3Q19 uses the 18 k with |c|^2 <= 2, D3Q27 the 26 k != 13.
+ *  - Every pointer argument named d_* or documented as "device" is device
+ *    memory owned by the caller.  The library never allocates device memory;
+ *    scratch comes from the caller's workspace (see geo_workspace_size).
+ *  - Every call is enqueued on the given stream (a hipStream_t; NULL is the
+ *    null stream) and returns without synchronising.
+ *  - Return value: GEO_OK, or a negative status for arguments that fail the
+ *    host-side checks (nothing is enqueued then), a too small workspace, or a
+ *    HIP launch error.
+ *  - Capacity overflow is reported on the device: the required number of
+ *    entries is written to the given int64 device counter, entries at index
+ *    >= cap are never written, and the caller re-runs with a larger buffer.
+ *  - Mesh contract (Methodology, "Overview" and "Voxelization and Near-Wall
+ *    Refinement"): closed, oriented with outward normals (counter-clockwise
+ *    seen from outside), not self-intersecting; every vertex coordinate lies in
+ *    [2^-12, n0] or is 0.  Zero-area triangles are allowed and ignored.  A
+ *    violation gives unspecified flags but never an out-of-bounds access;
+ *    vertex-range violations are counted in d_stats[GEO_STAT_CONTRACT].
+ *  - Results of geo_voxelize, geo_refine_flags and the integer outputs of
+ *    geo_cutlinks are exact (identical to the plain definitions evaluated in
+ *    exact arithmetic); link_q is within 1e-5 of the exact value.
+ */
+#ifndef GEO_H
+#define GEO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* geo_stream_t; /* hipStream_t */
+
+enum {
+    GEO_OK = 0,
+    GEO_ERR_ARG = -1,       /* host-side argument check failed; nothing enqueued */
+    GEO_ERR_WORKSPACE = -2, /* workspace smaller than geo_workspace_size(...)   */
+    GEO_ERR_DEVICE = -3     /* a HIP call or kernel launch failed                */
+};
+
+enum { GEO_F32 = 0, GEO_F64 = 1 };                 /* vertex storage type      */
+enum { GEO_PREC_F64 = 0, GEO_PREC_F32_FALLBACK = 1 }; /* arithmetic form        */
+enum { GEO_BINS_ROWS = 0, GEO_BINS_LINKS = 1 };    /* kind of bins             */
+
+/* workspace query selectors */
+enum { GEO_CALL_BINS_ROWS = 0, GEO_CALL_BINS_LINKS = 1, GEO_CALL_REFINE = 2, GEO_CALL_CUTLINKS = 3 };
+
+/* device statistics counters (uint64 each) */
+enum {
+    GEO_STAT_F32_TO_F64 = 0, /* float32 sign tests re-evaluated in float64          */
+    GEO_STAT_EXACT = 1,      /* float64 sign tests resolved by exact arithmetic     */
+    GEO_STAT_Q_F64 = 2,      /* q values recomputed in float64 (ill-conditioned)    */
+    GEO_STAT_CONTRACT = 3,   /* vertex coordinates outside the documented range     */
+    GEO_NSTATS = 4
+};
+
+#define GEO_MAX_LEVELS 12
+#define GEO_MAX_RES 32767 /* n0[a] * 2^level must not exceed this */
+
+typedef struct {
+    int32_t nv;          /* number of vertices                                     */
+    int32_t nt;          /* number of triangles                                    */
+    int32_t vdtype;      /* GEO_F32 or GEO_F64                                     */
+    const void* verts;   /* device [nv][3] float or double                         */
+    const int32_t* tris; /* device [nt][3] vertex indices, outward CCW             */
+} geo_mesh;
+
+/* One level of the forest.  Blocks of level 0 are all (n0/4)^3 blocks with bx
+ * fastest (geo_level0_blocks); blocks of level L+1 are the children of the
+ * refined blocks of level L, in parent order, octant o = ox + 2 oy + 4 oz
+ * (geo_refine_flags).  child[l] (l < level) are the child maps of the coarser
+ * levels: child[l][b] = index in level l+1 of the first child of block b of
+ * level l, or -1; they let a kernel find any block of this level from its
+ * coordinates (the paper's neighbour-children indices). */
+typedef struct {
+    int32_t n0[3];                        /* base cells per axis, multiples of 4 */
+    int32_t level;                        /* L, 0 <= L < GEO_MAX_LEVELS          */
+    int32_t nblocks;                      /* blocks on this level                */
+    const int32_t* bcoord;                /* device [nblocks][3]                 */
+    const int32_t* child[GEO_MAX_LEVELS]; /* device child maps of levels < L     */
+} geo_level;
+
+/* Compressed bins (CSR).  ROWS: one key per x-row line (j, k) of the level,
+ * key = j + ny * k with ny = n0y 2^L (lines of the whole domain); LINKS: one
+ * key per block of the level. */
+typedef struct {
+    int32_t kind;     /* GEO_BINS_ROWS or GEO_BINS_LINKS                          */
+    int64_t nkeys;    /* ROWS: ny*nz lines; LINKS: nblocks                          */
+    int32_t* off;     /* device [nkeys+1] offsets into val                          */
+    int32_t* val;     /* device [cap] entries                                       */
+    int64_t cap;      /* capacity of val                                            */
+    int64_t* d_count; /* device int64: number of entries needed                     */
+} geo_bins;
+
+/* Bytes of workspace needed by a call (selector GEO_CALL_*), for nkeys keys
+ * (ROWS: lines, LINKS/REFINE/CUTLINKS: blocks) and cap entries. */
+size_t geo_workspace_size(int32_t call, int64_t nkeys, int64_t cap);
+
+/* Eq. 3 with the block length 4 dx_L: N_prop = 1 + floor(d_spec / (4 sqrt 2)),
+ * level-independent, d_spec in base cells; the floor is taken exactly. */
+int32_t geo_nprop(double d_spec);
+
+/* Fill bcoord[(n0x/4)(n0y/4)(n0z/4)][3] with the level-0 blocks, bx fastest. */
+int geo_level0_blocks(const int32_t n0[3], int32_t* bcoord, geo_stream_t stream);
+
+/*
+ * Spatial binning (Methodology, "Spatial Binning"; Algorithm 2 for the
+ * widened block cover).
+ *
+ * ROWS: for every x-row line (j, k) of level L (line point y = (j+1/2)h,
+ *   z = (k+1/2)h), the list of surface events along the line, exactly:
+ *     - a parity event m >= 1 (int32 >= 0) for each triangle whose closed
+ *       yz-projection contains the line point after the symbolic perturbation
+ *       (y, z) -> (y + e, z + e^2), where m is the number of cell centres of
+ *       the line strictly left of the crossing (cells i < m see the crossing
+ *       ahead on their +x ray);
+ *     - a surface interval (int32 < 0: bit 31 set, lo in bits 0-14, hi in
+ *       bits 15-29) of cells whose centres lie on the closed triangle.
+ *   The entry order within a line is unspecified.  The arithmetic form is
+ *   selected by precision; both give identical entries.
+ * LINKS: for every block of the level, the ids of the triangles that overlap
+ *   the block's box widened by h on every side (conservative).
+ *
+ * mesh, lv: inputs (device arrays).  out: CSR with out->nkeys as above.
+ * d_stats: device uint64[GEO_NSTATS], accumulated (may be NULL).
+ */
+int geo_build_bins(const geo_mesh* mesh, const geo_level* lv, int32_t kind, int32_t precision,
+                   geo_bins* out, uint64_t* d_stats, void* ws, size_t ws_bytes,
+                   geo_stream_t stream);
+
+/*
+ * Solid voxelization of level L (Methodology, "Partial Surface Voxelization"
+ * and "External Cell Flag Propagation"; the result is the cell-centre
+ * membership in the closed solid that those steps approximate): solid[b] bit t
+ * is set iff the centre of cell t of block b lies in the closed solid bounded
+ * by the mesh.  rows: ROWS bins of the same level.  solid: device
+ * uint64[nblocks].  Integer work only.
+ */
+int geo_voxelize(const geo_level* lv, const geo_bins* rows, uint64_t* solid, geo_stream_t stream);
+
+/*
+ * Refinement flagging (Methodology, "Refinement Flagging and Propagation",
+ * Eq. 3): block classes, refinement marks and the children of level L+1.
+ *   bclass[b]: 0 fluid, 1 solid (>= 1 solid cell), 2 solid-boundary (solid
+ *     with a fully fluid neighbour block), 3 solid-adjacent (fluid block next
+ *     to a solid-boundary block);
+ *   marks: M1 = (solid-boundary and eligible) or next to a solid-boundary
+ *     block; then n_prop synchronous passes adding fluid blocks (and, in the
+ *     first pass, solid blocks) next to a marked block; refine = marked and
+ *     eligible, where eligible means every in-domain neighbour of the
+ *     26-neighbourhood exists on this level (2:1 balance);
+ *   child_map[b]: index of the first child in level L+1, or -1;
+ *   child_bcoord: device [8*nblocks][3] capacity, children in parent order,
+ *     octant o = ox + 2 oy + 4 oz; *d_nchild (device int64) = number written.
+ */
+int geo_refine_flags(const geo_level* lv, const uint64_t* solid, int32_t n_prop, uint8_t* bclass,
+                     uint8_t* refine, int32_t* child_map, int32_t* child_bcoord,
+                     int64_t* d_nchild, void* ws, size_t ws_bytes, geo_stream_t stream);
+
+/*
+ * Cut links of level L (Methodology, "Boundary Cell Identification", "Memory
+ * Allocations for Boundary Cells", "Link-Length Computation", Eq. 2).
+ *   link_mask[b*64+t] bit k: cell t of block b is fluid and the same-level
+ *     centre x + h c_k is solid (classified from the ROWS bins, also where
+ *     that centre's block does not exist; centres outside the domain are fluid);
+ *   the table lists every set bit in the order (block, t, k):
+ *     link_cell = b*64 + t, link_dir = k,
+ *     link_q = min t in (0,1] with x + t h c_k on the surface,
+ *     link_tri = a triangle attaining it (the smallest index at exact ties);
+ *   *d_nlinks (device int64) = number of links; entries >= cap not written.
+ * rows: ROWS bins of level L; links: LINKS bins of level L.
+ */
+int geo_cutlinks(const geo_mesh* mesh, const geo_level* lv, const geo_bins* rows,
+                 const geo_bins* links, int32_t lattice, int32_t precision, uint32_t* link_mask,
+                 int64_t cap, int64_t* d_nlinks, int32_t* link_cell, uint8_t* link_dir,
+                 float* link_q, int32_t* link_tri, uint64_t* d_stats, void* ws, size_t ws_bytes,
+                 geo_stream_t stream);
+
+/*
+ * Backward of q with respect to the vertices (not in the paper): for each
+ * link i with hit triangle (v0, v1, v2), barycentrics lambda of the hit point
+ * and normal n, grad_verts[v_j] += grad_q[i] * lambda_j * n / (n . h c_k)
+ * (float32 atomic adds; grad_verts device float[nv][3], accumulated).
+ */
+int geo_cutlinks_backward(const geo_mesh* mesh, const geo_level* lv, int64_t n_links,
+                          const int32_t* link_cell, const uint8_t* link_dir,
+                          const int32_t* link_tri, const float* grad_q, float* grad_verts,
+                          geo_stream_t stream);
+
+const char* geo_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,169 @@
+// C-ABI entry points of libgeo: host-side argument checks, workspace
+// partitioning and kernel launches (declared in include/geo.h).
+#include <math.h>
+
+#include "geo_internal.h"
+
+size_t geo_refine_ws_bytes(int64_t nb);
+size_t geo_cutlinks_ws_bytes(int64_t nb);
+
+namespace {
+
+inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t bins_ws_bytes(int64_t nkeys, int64_t cap) {
+    return al(sizeof(int2) * (size_t)(cap > 0 ? cap : 0)) + al(sizeof(int32_t) * ((size_t)nkeys + 1)) +
+           al(geo_scan_partials_bytes(nkeys));
+}
+
+bool check_level(const geo_level* lv) {
+    if (!lv) return false;
+    if (lv->level < 0 || lv->level >= GEO_MAX_LEVELS || lv->nblocks < 0) return false;
+    for (int a = 0; a < 3; a++) {
+        if (lv->n0[a] <= 0 || lv->n0[a] % 4 != 0) return false;
+        if ((int64_t)lv->n0[a] << lv->level > GEO_MAX_RES) return false;
+    }
+    if (lv->nblocks > 0 && !lv->bcoord) return false;
+    if ((int64_t)lv->nblocks * 64 > INT32_MAX) return false;
+    for (int l = 0; l < lv->level; l++)
+        if (!lv->child[l]) return false;
+    return true;
+}
+
+bool check_mesh(const geo_mesh* m) {
+    if (!m) return false;
+    if (m->nv < 0 || m->nt < 0) return false;
+    if (m->vdtype != GEO_F32 && m->vdtype != GEO_F64) return false;
+    if (m->nt > 0 && (!m->tris || !m->verts || m->nv == 0)) return false;
+    if ((int64_t)m->nt * 3 > INT32_MAX || (int64_t)m->nv * 3 > INT32_MAX) return false;
+    return true;
+}
+
+bool check_bins(const geo_bins* b, int kind, int64_t nkeys) {
+    if (!b || b->kind != kind || b->nkeys != nkeys || !b->off || !b->d_count || b->cap < 0) return false;
+    if (b->cap > 0 && !b->val) return false;
+    if (b->cap > INT32_MAX) return false;
+    return true;
+}
+
+int64_t row_keys(const geo_level* lv) {
+    return ((int64_t)lv->n0[1] << lv->level) * ((int64_t)lv->n0[2] << lv->level);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t geo_workspace_size(int32_t call, int64_t nkeys, int64_t cap) {
+    if (nkeys < 0) return 0;
+    switch (call) {
+        case GEO_CALL_BINS_ROWS:
+        case GEO_CALL_BINS_LINKS: return bins_ws_bytes(nkeys, cap);
+        case GEO_CALL_REFINE: return geo_refine_ws_bytes(nkeys);
+        case GEO_CALL_CUTLINKS: return geo_cutlinks_ws_bytes(nkeys);
+        default: return 0;
+    }
+}
+
+int32_t geo_nprop(double d_spec) {
+    // N_prop - 1 = largest k >= 0 with k 4 sqrt(2) <= d_spec, i.e. 32 k^2 <= d_spec^2
+    if (!(d_spec > 0) || !isfinite(d_spec)) return 1;
+    int64_t k = (int64_t)floor(d_spec / (4.0 * sqrt(2.0)));
+    if (k < 0) k = 0;
+    // exact comparison of 32 k^2 with d^2 = p + e (p = d*d, e = fma(d, d, -p))
+    auto le = [&](int64_t kk) {
+        const double lhs = 32.0 * (double)kk * (double)kk;  // exact for kk < 2^24
+        const double p = d_spec * d_spec, e = fma(d_spec, d_spec, -p);
+        return lhs < p || (lhs == p && e >= 0);
+    };
+    while (k > 0 && !le(k)) k--;
+    while (le(k + 1)) k++;
+    return (int32_t)(1 + k);
+}
+
+int geo_level0_blocks(const int32_t n0[3], int32_t* bcoord, geo_stream_t stream) {
+    if (!n0 || !bcoord) return GEO_ERR_ARG;
+    for (int a = 0; a < 3; a++)
+        if (n0[a] <= 0 || n0[a] % 4 != 0 || n0[a] > GEO_MAX_RES) return GEO_ERR_ARG;
+    return launch_level0(n0, bcoord, (hipStream_t)stream);
+}
+
+int geo_build_bins(const geo_mesh* mesh, const geo_level* lv, int32_t kind, int32_t precision, geo_bins* out,
+                   uint64_t* d_stats, void* ws, size_t ws_bytes, geo_stream_t stream) {
+    if (!check_mesh(mesh) || !check_level(lv)) return GEO_ERR_ARG;
+    if (kind != GEO_BINS_ROWS && kind != GEO_BINS_LINKS) return GEO_ERR_ARG;
+    if (precision != GEO_PREC_F64 && precision != GEO_PREC_F32_FALLBACK) return GEO_ERR_ARG;
+    const int64_t nkeys = kind == GEO_BINS_ROWS ? row_keys(lv) : (int64_t)lv->nblocks;
+    if (!check_bins(out, kind, nkeys)) return GEO_ERR_ARG;
+    if (nkeys + 1 > INT32_MAX) return GEO_ERR_ARG;
+    if (ws_bytes < bins_ws_bytes(nkeys, out->cap) || (!ws && ws_bytes)) return GEO_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    char* p = static_cast<char*>(ws);
+    int2* pairs = reinterpret_cast<int2*>(p);
+    p += al(sizeof(int2) * (size_t)out->cap);
+    int32_t* cnt = reinterpret_cast<int32_t*>(p);
+    p += al(sizeof(int32_t) * ((size_t)nkeys + 1));
+    int32_t* partials = reinterpret_cast<int32_t*>(p);
+    const DevMesh m = dev_mesh(mesh);
+    const DevLevel d = dev_level(lv);
+    int rc;
+    if ((rc = geo_fill_u64(reinterpret_cast<uint64_t*>(out->d_count), 0, 1, s)) != GEO_OK) return rc;
+    if ((rc = geo_fill_i32(cnt, 0, nkeys, s)) != GEO_OK) return rc;
+    if ((rc = launch_check_mesh(m, d, d_stats, s)) != GEO_OK) return rc;
+    if (kind == GEO_BINS_ROWS)
+        rc = launch_rows_pass1(m, d, precision, cnt, pairs, out->cap, out->d_count, d_stats, s);
+    else
+        rc = launch_links_pass1(m, d, cnt, pairs, out->cap, out->d_count, s);
+    if (rc != GEO_OK) return rc;
+    if ((rc = geo_scan_exclusive(cnt, out->off, nkeys, partials, s)) != GEO_OK) return rc;
+    return launch_bins_scatter(pairs, out->cap, out->d_count, out->off, cnt, out->val, s);
+}
+
+int geo_voxelize(const geo_level* lv, const geo_bins* rows, uint64_t* solid, geo_stream_t stream) {
+    if (!check_level(lv) || !check_bins(rows, GEO_BINS_ROWS, row_keys(lv))) return GEO_ERR_ARG;
+    if (lv->nblocks > 0 && !solid) return GEO_ERR_ARG;
+    return launch_voxelize(dev_level(lv), rows->off, rows->val, rows->cap, solid, (hipStream_t)stream);
+}
+
+int geo_refine_flags(const geo_level* lv, const uint64_t* solid, int32_t n_prop, uint8_t* bclass, uint8_t* refine,
+                     int32_t* child_map, int32_t* child_bcoord, int64_t* d_nchild, void* ws, size_t ws_bytes,
+                     geo_stream_t stream) {
+    if (!check_level(lv) || n_prop < 0 || !d_nchild) return GEO_ERR_ARG;
+    if (lv->level + 1 >= GEO_MAX_LEVELS) return GEO_ERR_ARG;
+    for (int a = 0; a < 3; a++)
+        if ((int64_t)lv->n0[a] << (lv->level + 1) > GEO_MAX_RES) return GEO_ERR_ARG;
+    if ((int64_t)lv->nblocks * 8 > INT32_MAX / 64) return GEO_ERR_ARG;
+    if (lv->nblocks > 0 && (!solid || !bclass || !refine || !child_map || !child_bcoord)) return GEO_ERR_ARG;
+    if (ws_bytes < geo_refine_ws_bytes(lv->nblocks) || (!ws && ws_bytes)) return GEO_ERR_WORKSPACE;
+    return launch_refine(dev_level(lv), solid, n_prop, bclass, refine, child_map, child_bcoord, d_nchild, ws, ws_bytes,
+                         (hipStream_t)stream);
+}
+
+int geo_cutlinks(const geo_mesh* mesh, const geo_level* lv, const geo_bins* rows, const geo_bins* links,
+                 int32_t lattice, int32_t precision, uint32_t* link_mask, int64_t cap, int64_t* d_nlinks,
+                 int32_t* link_cell, uint8_t* link_dir, float* link_q, int32_t* link_tri, uint64_t* d_stats,
+                 void* ws, size_t ws_bytes, geo_stream_t stream) {
+    if (!check_mesh(mesh) || !check_level(lv)) return GEO_ERR_ARG;
+    if (!check_bins(rows, GEO_BINS_ROWS, row_keys(lv)) || !check_bins(links, GEO_BINS_LINKS, lv->nblocks))
+        return GEO_ERR_ARG;
+    if (lattice != 19 && lattice != 27) return GEO_ERR_ARG;
+    if (precision != GEO_PREC_F64 && precision != GEO_PREC_F32_FALLBACK) return GEO_ERR_ARG;
+    if (cap < 0 || !d_nlinks || (lv->nblocks > 0 && !link_mask)) return GEO_ERR_ARG;
+    if (cap > 0 && (!link_cell || !link_dir || !link_q || !link_tri)) return GEO_ERR_ARG;
+    if (ws_bytes < geo_cutlinks_ws_bytes(lv->nblocks) || (!ws && ws_bytes)) return GEO_ERR_WORKSPACE;
+    return launch_cutlinks(dev_mesh(mesh), dev_level(lv), rows, links, lattice, precision, link_mask, cap, d_nlinks,
+                           link_cell, link_dir, link_q, link_tri, d_stats, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int geo_cutlinks_backward(const geo_mesh* mesh, const geo_level* lv, int64_t n_links, const int32_t* link_cell,
+                          const uint8_t* link_dir, const int32_t* link_tri, const float* grad_q, float* grad_verts,
+                          geo_stream_t stream) {
+    if (!check_mesh(mesh) || !check_level(lv) || n_links < 0) return GEO_ERR_ARG;
+    if (n_links > 0 && (!link_cell || !link_dir || !link_tri || !grad_q || !grad_verts)) return GEO_ERR_ARG;
+    return launch_backward(dev_mesh(mesh), dev_level(lv), n_links, link_cell, link_dir, link_tri, grad_q, grad_verts,
+                           (hipStream_t)stream);
+}
+
+const char* geo_version(void) { return "libgeo 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,512 @@
+// Spatial binning on gfx950 (Methodology, "Spatial Binning").
+//
+// ROWS bins hold, per x-row line of a level, the exact surface events along
+// the line (parity crossings and on-surface intervals); they are built
+// triangle-parallel: each triangle visits the row lines inside its yz
+// bounding box, decides exactly whether the line meets it, and where along
+// the line.  LINKS bins hold, per block, the triangles overlapping the block
+// box widened by one cell (the widened bin cover of Algorithm 2).
+//
+// Both are counting sorts without a global sort: pass 1 appends (key, value)
+// pairs with one atomic per wave and counts per key, an exclusive scan turns
+// counts into offsets, and a scatter pass places the pairs.
+#include <type_traits>
+
+#include "geo_internal.h"
+
+namespace {
+
+// ------------------------------------------------------------------------
+// wave-aggregated append of (key, value) pairs
+// ------------------------------------------------------------------------
+__device__ __forceinline__ void wave_append(bool has, int key, int32_t val, int2* pairs, int64_t cap,
+                                            int64_t* d_count, int32_t* cnt) {
+    const unsigned long long mask = __ballot(has);
+    if (mask == 0ull) return;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)mask) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd((unsigned long long*)d_count, (unsigned long long)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    if (has) {
+        const unsigned long long pos = base + __popcll(mask & ((1ull << lane) - 1ull));
+        if (pos < (unsigned long long)cap) pairs[pos] = make_int2(key, val);
+        atomicAdd(&cnt[key], 1);
+    }
+}
+
+// ------------------------------------------------------------------------
+// per-triangle local frame for the row pass
+// ------------------------------------------------------------------------
+template <typename R>
+struct RowTri {
+    R v[3][3];    // local coordinates (level-L cell units, centres at integers)
+    R delta;      // bound on |v - exact| (0 when exact)
+    int o[3];     // integer origin of the local frame
+    int idx[3];   // vertex ids in local order (b and c swapped when the yz area is negative)
+};
+
+// exact scaled coordinate X = v 2^L - 1/2 of vertex vid, axis a, in float64
+__device__ __forceinline__ double scaled64(const DevMesh& m, int vid, int a, double s) {
+    return load_coord(m, vid, a) * s - 0.5;
+}
+
+// exact float64 local coordinates of T (reloaded from memory)
+template <typename R>
+__device__ __forceinline__ void local64(const DevMesh& m, const RowTri<R>& T, double s, double v[3][3]) {
+    for (int i = 0; i < 3; i++)
+        for (int a = 0; a < 3; a++) v[i][a] = scaled64(m, T.idx[i], a, s) - (double)T.o[a];
+}
+
+struct Stats {
+    unsigned fb = 0, ex = 0;
+};
+
+// exact sign of orient2d in the (y,z) plane of local points p, q and (py, pz)
+template <typename R>
+__device__ __forceinline__ int chain_o2_yz(const DevMesh& m, const RowTri<R>& T, double s, int i, int j,
+                                           int py, int pz, Stats& st) {
+    int r = orient2d_filter<R>(T.v[i][1], T.v[i][2], T.v[j][1], T.v[j][2], (R)py, (R)pz, T.delta);
+    if (r != 0) return r;
+    double v[3][3];
+    if constexpr (std::is_same<R, float>::value) {
+        st.fb++;
+        local64(m, T, s, v);
+        r = orient2d_filter<double>(v[i][1], v[i][2], v[j][1], v[j][2], (double)py, (double)pz, 0.0);
+        if (r != 0) return r;
+    } else {
+        local64(m, T, s, v);
+    }
+    st.ex++;
+    return orient2d_exact(v[i][1], v[i][2], v[j][1], v[j][2], (double)py, (double)pz);
+}
+
+// exact sign of orient3d(v0, v1, v2, P) with local P = (px, py, pz)
+template <typename R>
+__device__ __forceinline__ int chain_o3(const DevMesh& m, const RowTri<R>& T, double s, int px, int py,
+                                        int pz, Stats& st) {
+    R P[3] = {(R)px, (R)py, (R)pz};
+    int r = orient3d_filter<R>(T.v[0], T.v[1], T.v[2], P, T.delta);
+    if (r != 0) return r;
+    double v[3][3];
+    double P64[3] = {(double)px, (double)py, (double)pz};
+    if constexpr (std::is_same<R, float>::value) {
+        st.fb++;
+        local64(m, T, s, v);
+        r = orient3d_filter<double>(v[0], v[1], v[2], P64, 0.0);
+        if (r != 0) return r;
+    } else {
+        local64(m, T, s, v);
+    }
+    st.ex++;
+    return orient3d_exact(v[0], v[1], v[2], P64);
+}
+
+// exact sign of orient2d on axes (a0, a1) of the three local vertices
+template <typename R>
+__device__ __forceinline__ int chain_area(const DevMesh& m, const RowTri<R>& T, double s, int a0, int a1,
+                                          Stats& st) {
+    int r = orient2d_filter<R>(T.v[0][a0], T.v[0][a1], T.v[1][a0], T.v[1][a1], T.v[2][a0], T.v[2][a1],
+                               T.delta);
+    if (r != 0) return r;
+    double v[3][3];
+    local64(m, T, s, v);
+    if constexpr (std::is_same<R, float>::value) {
+        st.fb++;
+        r = orient2d_filter<double>(v[0][a0], v[0][a1], v[1][a0], v[1][a1], v[2][a0], v[2][a1], 0.0);
+        if (r != 0) return r;
+    }
+    st.ex++;
+    return orient2d_exact(v[0][a0], v[0][a1], v[1][a0], v[1][a1], v[2][a0], v[2][a1]);
+}
+
+// exact sign of orient2d on axes (a0, a1) of local vertices i, j and point (p0, p1)
+template <typename R>
+__device__ __forceinline__ int chain_o2_axes(const DevMesh& m, const RowTri<R>& T, double s, int i, int j,
+                                             int a0, int a1, int p0, int p1, Stats& st) {
+    int r = orient2d_filter<R>(T.v[i][a0], T.v[i][a1], T.v[j][a0], T.v[j][a1], (R)p0, (R)p1, T.delta);
+    if (r != 0) return r;
+    double v[3][3];
+    local64(m, T, s, v);
+    if constexpr (std::is_same<R, float>::value) {
+        st.fb++;
+        r = orient2d_filter<double>(v[i][a0], v[i][a1], v[j][a0], v[j][a1], (double)p0, (double)p1, 0.0);
+        if (r != 0) return r;
+    }
+    st.ex++;
+    return orient2d_exact(v[i][a0], v[i][a1], v[j][a0], v[j][a1], (double)p0, (double)p1);
+}
+
+// Simulation-of-simplicity sign of the yz edge function of u->w at a point
+// where it vanishes exactly: the point is moved to (y + e, z + e^2), so
+// E changes by -(w_z - u_z) e + (w_y - u_y) e^2.
+template <typename R>
+__device__ __forceinline__ int sos_tie(const DevMesh& m, const RowTri<R>& T, double s, int i, int j) {
+    double v[3][3];
+    local64(m, T, s, v);
+    const double dz = v[j][2] - v[i][2], dy = v[j][1] - v[i][1];  // exact comparisons via signs
+    if (v[j][2] != v[i][2]) return dz > 0 ? -1 : 1;
+    if (v[j][1] != v[i][1]) return dy > 0 ? 1 : -1;
+    return 0;
+}
+
+// Set up the local frame.  Returns false for triangles with no line.
+template <typename R>
+__device__ bool row_setup(const DevMesh& m, int t, int L, int ny, int nz, RowTri<R>& T, int& jlo,
+                          int& jhi, int& klo, int& khi) {
+    const double s = ldexp(1.0, L);
+    int id[3] = {m.tris[3 * (int64_t)t], m.tris[3 * (int64_t)t + 1], m.tris[3 * (int64_t)t + 2]};
+    double X[3][3];
+    for (int i = 0; i < 3; i++)
+        for (int a = 0; a < 3; a++) X[i][a] = scaled64(m, id[i], a, s);
+    const double ymin = fmin(X[0][1], fmin(X[1][1], X[2][1])), ymax = fmax(X[0][1], fmax(X[1][1], X[2][1]));
+    const double zmin = fmin(X[0][2], fmin(X[1][2], X[2][2])), zmax = fmax(X[0][2], fmax(X[1][2], X[2][2]));
+    jlo = (int)fmax(ceil(ymin), 0.0);
+    jhi = (int)fmin(floor(ymax), (double)(ny - 1));
+    klo = (int)fmax(ceil(zmin), 0.0);
+    khi = (int)fmin(floor(zmax), (double)(nz - 1));
+    if (jlo > jhi || klo > khi) return false;
+    // origin: x from vertex 0, y/z from the first line; fall back to 0 on an
+    // axis where the translation would not be exact in float64
+    int o[3] = {(int)floor(X[0][0]), jlo, klo};
+    for (int a = 0; a < 3; a++) {
+        bool exact = true;
+        for (int i = 0; i < 3; i++) {
+            // Knuth's two-sum error of X - o: zero iff the difference is exact
+            const double sum = X[i][a] - (double)o[a];
+            const double bb = sum - X[i][a];
+            const double err = (X[i][a] - (sum - bb)) + (-(double)o[a] - bb);
+            if (err != 0.0) exact = false;
+        }
+        if (!exact) o[a] = 0;
+    }
+    R delta = 0;
+    for (int i = 0; i < 3; i++) {
+        T.idx[i] = id[i];
+        for (int a = 0; a < 3; a++) {
+            const double x = X[i][a] - (double)o[a];
+            T.v[i][a] = (R)x;
+            const double err = fabs((double)T.v[i][a] - x);
+            // round the bound up when stored in float
+            if ((R)err < err) delta = geo_max(delta, (R)(err * (1.0 + 1e-6)));
+            else delta = geo_max(delta, (R)err);
+        }
+    }
+    T.delta = delta;
+    for (int a = 0; a < 3; a++) T.o[a] = o[a];
+    return true;
+}
+
+template <typename R>
+__device__ __forceinline__ void swap_bc(RowTri<R>& T) {
+    for (int a = 0; a < 3; a++) {
+        R tmp = T.v[1][a];
+        T.v[1][a] = T.v[2][a];
+        T.v[2][a] = tmp;
+    }
+    int ti = T.idx[1];
+    T.idx[1] = T.idx[2];
+    T.idx[2] = ti;
+}
+
+// events of one (triangle, line) pair; e0: parity event or none, e1: surface interval or none
+template <typename R>
+__device__ void row_events(const DevMesh& m, const RowTri<R>& T, double s, int mode, int drop, int areaSign,
+                           int j, int k, int nx, Stats& st, bool& has0, int32_t& e0, bool& has1, int32_t& e1) {
+    has0 = has1 = false;
+    const int py = j - T.o[1], pz = k - T.o[2];
+    R xmn = geo_min(T.v[0][0], geo_min(T.v[1][0], T.v[2][0])) - T.delta;
+    R xmx = geo_max(T.v[0][0], geo_max(T.v[1][0], T.v[2][0])) + T.delta;
+    if (mode == 1) {
+        // proper yz projection (counter-clockwise after set-up)
+        int e[3];
+        for (int i = 0; i < 3; i++) {
+            e[i] = chain_o2_yz<R>(m, T, s, i, (i + 1) % 3, py, pz, st);
+            if (e[i] < 0) return;
+        }
+        bool sos_in = true;
+        for (int i = 0; i < 3; i++)
+            if (e[i] == 0 && sos_tie<R>(m, T, s, i, (i + 1) % 3) <= 0) sos_in = false;
+        // crossing position: smallest integer c with orient3d(T, (c, py, pz)) <= 0
+        // (x_hit <= c); orient3d is n_x (x_hit - x) with n_x > 0.
+        const R e1x = T.v[1][0] - T.v[0][0], e1y = T.v[1][1] - T.v[0][1], e1z = T.v[1][2] - T.v[0][2];
+        const R e2x = T.v[2][0] - T.v[0][0], e2y = T.v[2][1] - T.v[0][1], e2z = T.v[2][2] - T.v[0][2];
+        const R nx_ = e1y * e2z - e1z * e2y, ny_ = e1z * e2x - e1x * e2z, nz_ = e1x * e2y - e1y * e2x;
+        const int lo = (int)ceil((double)xmn), hi = (int)ceil((double)xmx);
+        R xs = T.v[0][0] - (ny_ * ((R)py - T.v[0][1]) + nz_ * ((R)pz - T.v[0][2])) / nx_;
+        int c;
+        if (!(xs == xs) || xs < (R)lo) c = lo;
+        else if (xs > (R)hi) c = hi;
+        else c = (int)ceil((double)xs);
+        int sc = chain_o3<R>(m, T, s, c, py, pz, st);
+        if (sc > 0) {
+            do {
+                c++;
+                sc = chain_o3<R>(m, T, s, c, py, pz, st);
+            } while (sc > 0 && c < hi + 1);
+        } else {
+            while (c > lo) {
+                const int sp = chain_o3<R>(m, T, s, c - 1, py, pz, st);
+                if (sp > 0) break;
+                c--;
+                sc = sp;
+            }
+        }
+        const int g = c + T.o[0];  // global index of the first centre at or right of the crossing
+        if (sos_in && g >= 1) {
+            has0 = true;
+            e0 = g < nx ? g : nx;
+        }
+        if (sc == 0 && g >= 0 && g < nx) {
+            has1 = true;
+            e1 = row_surf_entry(g, g);
+        }
+        return;
+    }
+    // mode 2: edge-on triangle (zero yz area, non-degenerate).  The line meets
+    // it only if the line point is on the projected segment; then every
+    // centre of the line inside the closed triangle is on the surface.
+    {
+        // longest projected edge (any edge with distinct yz endpoints works)
+        int bi = 0;
+        R best = -1;
+        for (int i = 0; i < 3; i++) {
+            const int jn = (i + 1) % 3;
+            const R l = geo_fabs(T.v[jn][1] - T.v[i][1]) + geo_fabs(T.v[jn][2] - T.v[i][2]);
+            if (l > best) { best = l; bi = i; }
+        }
+        if (chain_o2_yz<R>(m, T, s, bi, (bi + 1) % 3, py, pz, st) != 0) return;
+        const int pw = drop == 1 ? py : pz;  // coordinate kept beside x
+        int first = -1, last = -2;
+        const int lo = (int)ceil((double)xmn), hi = (int)floor((double)xmx);
+        for (int c = lo; c <= hi; c++) {
+            bool in = true;
+            for (int i = 0; i < 3 && in; i++) {
+                const int r = chain_o2_axes<R>(m, T, s, i, (i + 1) % 3, 0, drop, c, pw, st);
+                if (r * areaSign < 0) in = false;
+            }
+            if (in) {
+                if (first < 0) first = c;
+                last = c;
+            } else if (first >= 0) {
+                break;  // convex: the inside centres are contiguous
+            }
+        }
+        if (first >= 0) {
+            int gl = first + T.o[0], gh = last + T.o[0];
+            gl = gl < 0 ? 0 : gl;
+            gh = gh > nx - 1 ? nx - 1 : gh;
+            if (gl <= gh) {
+                has1 = true;
+                e1 = row_surf_entry(gl, gh);
+            }
+        }
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_rows_pass1(DevMesh m, DevLevel d, int32_t* cnt, int2* pairs,
+                                                    int64_t cap, int64_t* d_count, uint64_t* stats) {
+    const int L = d.level;
+    const int nx = d.n0[0] << L, ny = d.n0[1] << L, nz = d.n0[2] << L;
+    const double s = ldexp(1.0, L);
+    Stats st;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m.nt; base += stride) {
+        const int64_t t = base + threadIdx.x;
+        RowTri<R> T;
+        int jlo = 0, jhi = -1, klo = 0, khi = -1;
+        int mode = 0, drop = 0, areaSign = 0;
+        if (t < m.nt && row_setup<R>(m, (int)t, L, ny, nz, T, jlo, jhi, klo, khi)) {
+            const int ayz = chain_area<R>(m, T, s, 1, 2, st);
+            if (ayz < 0) swap_bc<R>(T);
+            if (ayz != 0) {
+                mode = 1;
+            } else {
+                // edge-on or degenerate: find a plane (x,y) or (x,z) with non-zero area
+                const int axy = chain_area<R>(m, T, s, 0, 1, st);
+                if (axy != 0) { mode = 2; drop = 1; areaSign = axy; }
+                else {
+                    const int axz = chain_area<R>(m, T, s, 0, 2, st);
+                    if (axz != 0) { mode = 2; drop = 2; areaSign = axz; }
+                }
+            }
+        }
+        const int nj = mode ? jhi - jlo + 1 : 0;
+        const int nlines = mode ? nj * (khi - klo + 1) : 0;
+        for (int it = 0; __any(it < nlines); it++) {
+            bool h0 = false, h1 = false;
+            int32_t e0 = 0, e1 = 0;
+            int key = 0;
+            if (it < nlines) {
+                const int j = jlo + it % nj, k = klo + it / nj;
+                key = j + ny * k;
+                row_events<R>(m, T, s, mode, drop, areaSign, j, k, nx, st, h0, e0, h1, e1);
+            }
+            wave_append(h0, key, e0, pairs, cap, d_count, cnt);
+            wave_append(h1, key, e1, pairs, cap, d_count, cnt);
+        }
+    }
+    if (stats) {
+        if constexpr (std::is_same<R, float>::value) wave_count(&stats[GEO_STAT_F32_TO_F64], st.fb);
+        wave_count(&stats[GEO_STAT_EXACT], st.ex);
+    }
+}
+
+// ------------------------------------------------------------------------
+// LINKS: triangle / widened block box overlap (separating axes, float64,
+// with an outward margin so that rounding can only add candidates)
+// ------------------------------------------------------------------------
+__device__ __forceinline__ bool axis_sep(double p0, double p1, double p2, double r) {
+    const double mn = fmin(p0, fmin(p1, p2)), mx = fmax(p0, fmax(p1, p2));
+    return mn > r || mx < -r;
+}
+
+__device__ bool tri_box_overlap(const double* c, double hs, const double v0in[3], const double v1in[3],
+                                const double v2in[3]) {
+    double v0[3], v1[3], v2[3];
+    for (int a = 0; a < 3; a++) {
+        v0[a] = v0in[a] - c[a];
+        v1[a] = v1in[a] - c[a];
+        v2[a] = v2in[a] - c[a];
+    }
+    // box face normals
+    for (int a = 0; a < 3; a++)
+        if (axis_sep(v0[a], v1[a], v2[a], hs)) return false;
+    const double e[3][3] = {{v1[0] - v0[0], v1[1] - v0[1], v1[2] - v0[2]},
+                            {v2[0] - v1[0], v2[1] - v1[1], v2[2] - v1[2]},
+                            {v0[0] - v2[0], v0[1] - v2[1], v0[2] - v2[2]}};
+    // nine edge cross axes: axis = e_box(a) x e(i)
+    for (int i = 0; i < 3; i++) {
+        for (int a = 0; a < 3; a++) {
+            double ax[3] = {0, 0, 0};
+            const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
+            ax[b1] = -e[i][b2];
+            ax[b2] = e[i][b1];
+            const double p0 = ax[0] * v0[0] + ax[1] * v0[1] + ax[2] * v0[2];
+            const double p1 = ax[0] * v1[0] + ax[1] * v1[1] + ax[2] * v1[2];
+            const double p2 = ax[0] * v2[0] + ax[1] * v2[1] + ax[2] * v2[2];
+            const double r = hs * (fabs(ax[0]) + fabs(ax[1]) + fabs(ax[2]));
+            if (axis_sep(p0, p1, p2, r * (1.0 + 1e-9))) return false;
+        }
+    }
+    // triangle plane
+    const double n[3] = {e[0][1] * e[1][2] - e[0][2] * e[1][1], e[0][2] * e[1][0] - e[0][0] * e[1][2],
+                         e[0][0] * e[1][1] - e[0][1] * e[1][0]};
+    const double dist = n[0] * v0[0] + n[1] * v0[1] + n[2] * v0[2];
+    const double r = hs * (fabs(n[0]) + fabs(n[1]) + fabs(n[2]));
+    if (fabs(dist) > r * (1.0 + 1e-9) + 1e-12 * (fabs(n[0]) + fabs(n[1]) + fabs(n[2]))) return false;
+    return true;
+}
+
+__global__ void __launch_bounds__(256) k_links_pass1(DevMesh m, DevLevel d, int32_t* cnt, int2* pairs,
+                                                     int64_t cap, int64_t* d_count) {
+    const int L = d.level;
+    const double h = ldexp(1.0, -L), bw = 4.0 * h;
+    const int nbx = (d.n0[0] >> 2) << L, nby = (d.n0[1] >> 2) << L, nbz = (d.n0[2] >> 2) << L;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m.nt; base += stride) {
+        const int64_t t = base + threadIdx.x;
+        double v[3][3];
+        int lo[3] = {0, 0, 0}, hi[3] = {-1, -1, -1};
+        if (t < m.nt) {
+            for (int i = 0; i < 3; i++) {
+                const int vid = m.tris[3 * t + i];
+                for (int a = 0; a < 3; a++) v[i][a] = load_coord(m, vid, a);
+            }
+            const int nb[3] = {nbx, nby, nbz};
+            for (int a = 0; a < 3; a++) {
+                const double mn = fmin(v[0][a], fmin(v[1][a], v[2][a])), mx = fmax(v[0][a], fmax(v[1][a], v[2][a]));
+                lo[a] = (int)floor((mn - 2.0 * h) / bw);
+                hi[a] = (int)floor((mx + 2.0 * h) / bw);
+                lo[a] = lo[a] < 0 ? 0 : lo[a];
+                hi[a] = hi[a] > nb[a] - 1 ? nb[a] - 1 : hi[a];
+            }
+        }
+        const int sx = hi[0] - lo[0] + 1, sy = hi[1] - lo[1] + 1, sz = hi[2] - lo[2] + 1;
+        const int n = (sx > 0 && sy > 0 && sz > 0) ? sx * sy * sz : 0;
+        for (int it = 0; __any(it < n); it++) {
+            bool has = false;
+            int key = 0;
+            if (it < n) {
+                const int bx = lo[0] + it % sx, by = lo[1] + (it / sx) % sy, bz = lo[2] + it / (sx * sy);
+                const int idx = forest_lookup(d, bx, by, bz);
+                if (idx >= 0) {
+                    // widened box [4bh - h, 4(b+1)h + h], plus a relative margin
+                    const double c[3] = {(bx + 0.5) * bw, (by + 0.5) * bw, (bz + 0.5) * bw};
+                    const double hs = (0.5 * bw + h) * (1.0 + 1e-9);
+                    has = tri_box_overlap(c, hs, v[0], v[1], v[2]);
+                    key = idx;
+                }
+            }
+            wave_append(has, key, (int32_t)t, pairs, cap, d_count, cnt);
+        }
+    }
+}
+
+__global__ void k_bins_scatter(const int2* pairs, int64_t cap, const int64_t* d_count, const int32_t* off,
+                               int32_t* cursor, int32_t* val) {
+    const int64_t n0 = *d_count;
+    const int64_t n = n0 < cap ? n0 : cap;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int2 p = pairs[i];
+        const int64_t pos = (int64_t)off[p.x] + (atomicSub(&cursor[p.x], 1) - 1);
+        if (pos >= 0 && pos < cap) val[pos] = p.y;
+    }
+}
+
+__global__ void k_check_mesh(DevMesh m, DevLevel d, uint64_t* stats) {
+    unsigned bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)m.nv * 3;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int a = (int)(i % 3);
+        const double x = load_coord(m, (int)(i / 3), a);
+        const bool ok = x == 0.0 || (x >= 0x1p-12 && x <= (double)d.n0[a]);
+        bad += ok ? 0u : 1u;
+    }
+    wave_count(&stats[GEO_STAT_CONTRACT], bad);
+}
+
+inline unsigned grid_for(int64_t n, int threads, int64_t maxg = 1 << 16) {
+    int64_t g = (n + threads - 1) / threads;
+    if (g > maxg) g = maxg;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+int launch_rows_pass1(const DevMesh& m, const DevLevel& d, int precision, int32_t* cnt, int2* pairs,
+                      int64_t cap, int64_t* d_count, uint64_t* d_stats, hipStream_t s) {
+    if (m.nt == 0) return GEO_OK;
+    const unsigned g = grid_for(m.nt, 256);
+    if (precision == GEO_PREC_F32_FALLBACK)
+        k_rows_pass1<float><<<g, 256, 0, s>>>(m, d, cnt, pairs, cap, d_count, d_stats);
+    else
+        k_rows_pass1<double><<<g, 256, 0, s>>>(m, d, cnt, pairs, cap, d_count, d_stats);
+    GEO_LAUNCH_CHECK();
+    return GEO_OK;
+}
+
+int launch_links_pass1(const DevMesh& m, const DevLevel& d, int32_t* cnt, int2* pairs, int64_t cap,
+                       int64_t* d_count, hipStream_t s) {
+    if (m.nt == 0) return GEO_OK;
+    k_links_pass1<<<grid_for(m.nt, 256), 256, 0, s>>>(m, d, cnt, pairs, cap, d_count);
+    GEO_LAUNCH_CHECK();
+    return GEO_OK;
+}
+
+int launch_bins_scatter(const int2* pairs, int64_t cap, const int64_t* d_count, const int32_t* off,
+                        int32_t* cursor, int32_t* val, hipStream_t s) {
+    if (cap <= 0) return GEO_OK;
+    k_bins_scatter<<<grid_for(cap, 256, 8192), 256, 0, s>>>(pairs, cap, d_count, off, cursor, val);
+    GEO_LAUNCH_CHECK();
+    return GEO_OK;
+}
+
+int launch_check_mesh(const DevMesh& m, const DevLevel& d, uint64_t* d_stats, hipStream_t s) {
+    if (!d_stats || m.nv == 0) return GEO_OK;
+    k_check_mesh<<<grid_for((int64_t)m.nv * 3, 256, 4096), 256, 0, s>>>(m, d, d_stats);
+    GEO_LAUNCH_CHECK();
+    return GEO_OK;
+}

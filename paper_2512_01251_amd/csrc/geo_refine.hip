@@ -1,0 +1,171 @@
+// Refinement flagging of one level (Methodology, "Refinement Flagging and
+// Propagation", Eq. 3), block-parallel (the paper's secondary access mode):
+//   1. 26-neighbour indices through the forest child maps, solid flag;
+//   2. solid-boundary (solid with a fully fluid neighbour) and eligibility
+//      (every in-domain neighbour exists: refining keeps the 2:1 balance);
+//   3. marks M1 = (solid-boundary and eligible) or next to a solid-boundary
+//      block; solid-adjacent class for the fluid ones;
+//   4. n_prop synchronous passes (double-buffered, as the paper avoids the
+//      read/write race): fluid blocks, and solid blocks in the first pass,
+//      join when a neighbour is marked;
+//   5. refine = marked and eligible; children emitted in parent order via an
+//      exclusive scan, octant o = ox + 2 oy + 4 oz.
+#include "geo_internal.h"
+
+namespace {
+
+enum { F_S = 1, F_SB = 2, F_EL = 4 };
+
+__device__ __forceinline__ void nbr_offset(int k, int& dx, int& dy, int& dz) {
+    const int kk = k < 13 ? k : k + 1;  // skip the centre of the 3x3x3 cube
+    dx = kk % 3 - 1;
+    dy = (kk / 3) % 3 - 1;
+    dz = kk / 9 - 1;
+}
+
+__global__ void k_ref_nbr(DevLevel d, const uint64_t* solid, int32_t* nbr, uint8_t* flags) {
+    const int64_t nb = d.nblocks;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+        const int bx = d.bcoord[3 * b], by = d.bcoord[3 * b + 1], bz = d.bcoord[3 * b + 2];
+        for (int k = 0; k < 26; k++) {
+            int dx, dy, dz;
+            nbr_offset(k, dx, dy, dz);
+            nbr[(int64_t)k * nb + b] = forest_lookup(d, bx + dx, by + dy, bz + dz);
+        }
+        flags[b] = solid[b] != 0ull ? F_S : 0;
+    }
+}
+
+__global__ void k_ref_class(int64_t nb, const int32_t* nbr, const uint8_t* flags, uint8_t* cls) {
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+        const uint8_t f = flags[b];
+        bool fluid_nbr = false, elig = true;
+        for (int k = 0; k < 26; k++) {
+            const int n = nbr[(int64_t)k * nb + b];
+            if (n == -1) elig = false;  // in-domain neighbour missing: refinement interface
+            if (n >= 0 && !(flags[n] & F_S)) fluid_nbr = true;
+        }
+        uint8_t g = f & F_S;
+        if ((f & F_S) && fluid_nbr) g |= F_SB;
+        if (elig) g |= F_EL;
+        cls[b] = g;
+    }
+}
+
+__global__ void k_ref_m1(int64_t nb, const int32_t* nbr, const uint8_t* flags, uint8_t* M, uint8_t* bclass) {
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+        const uint8_t f = flags[b];
+        bool adj = false;
+        for (int k = 0; k < 26; k++) {
+            const int n = nbr[(int64_t)k * nb + b];
+            if (n >= 0 && (flags[n] & F_SB)) adj = true;
+        }
+        const bool m0 = (f & F_SB) && (f & F_EL);
+        const bool m = m0 || adj;
+        M[b] = m ? 1 : 0;
+        bclass[b] = (f & F_SB) ? 2 : ((f & F_S) ? 1 : ((m && !m0) ? 3 : 0));
+    }
+}
+
+__global__ void k_ref_prop(int64_t nb, const int32_t* nbr, const uint8_t* flags, const uint8_t* Min,
+                           uint8_t* Mout, int first) {
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+        uint8_t m = Min[b];
+        if (!m && (!(flags[b] & F_S) || first)) {
+            for (int k = 0; k < 26; k++) {
+                const int n = nbr[(int64_t)k * nb + b];
+                if (n >= 0 && Min[n]) { m = 1; break; }
+            }
+        }
+        Mout[b] = m;
+    }
+}
+
+__global__ void k_ref_final(int64_t nb, const uint8_t* flags, const uint8_t* M, uint8_t* refine, int32_t* cnt) {
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (M[b] && (flags[b] & F_EL)) ? 1 : 0;
+        refine[b] = (uint8_t)r;
+        cnt[b] = r;
+    }
+}
+
+__global__ void k_ref_emit(DevLevel d, const uint8_t* refine, const int32_t* offs, int32_t* child_map,
+                           int32_t* child_bcoord, int64_t* d_nchild) {
+    const int64_t nb = d.nblocks;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+        if (!refine[b]) {
+            child_map[b] = -1;
+            continue;
+        }
+        const int64_t c0 = 8 * (int64_t)offs[b];
+        child_map[b] = (int32_t)c0;
+        const int bx = d.bcoord[3 * b], by = d.bcoord[3 * b + 1], bz = d.bcoord[3 * b + 2];
+        for (int o = 0; o < 8; o++) {
+            child_bcoord[3 * (c0 + o)] = 2 * bx + (o & 1);
+            child_bcoord[3 * (c0 + o) + 1] = 2 * by + ((o >> 1) & 1);
+            child_bcoord[3 * (c0 + o) + 2] = 2 * bz + ((o >> 2) & 1);
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *d_nchild = 8 * (int64_t)offs[nb];
+}
+
+inline unsigned grid_for(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+size_t geo_refine_ws_bytes(int64_t nb) {
+    return al(sizeof(int32_t) * 26 * (size_t)nb) + 4 * al((size_t)nb) + al(sizeof(int32_t) * (size_t)nb) +
+           al(sizeof(int32_t) * ((size_t)nb + 1)) + al(geo_scan_partials_bytes(nb));
+}
+
+int launch_refine(const DevLevel& d, const uint64_t* solid, int n_prop, uint8_t* bclass, uint8_t* refine,
+                  int32_t* child_map, int32_t* child_bcoord, int64_t* d_nchild, void* ws, size_t ws_bytes,
+                  hipStream_t s) {
+    const int64_t nb = d.nblocks;
+    if (ws_bytes < geo_refine_ws_bytes(nb)) return GEO_ERR_WORKSPACE;
+    char* p = static_cast<char*>(ws);
+    int32_t* nbr = reinterpret_cast<int32_t*>(p);
+    p += al(sizeof(int32_t) * 26 * (size_t)nb);
+    uint8_t* flags = reinterpret_cast<uint8_t*>(p);
+    p += al((size_t)nb);
+    uint8_t* cls = reinterpret_cast<uint8_t*>(p);
+    p += al((size_t)nb);
+    uint8_t* M = reinterpret_cast<uint8_t*>(p);
+    p += al((size_t)nb);
+    uint8_t* Mn = reinterpret_cast<uint8_t*>(p);
+    p += al((size_t)nb);
+    int32_t* cnt = reinterpret_cast<int32_t*>(p);
+    p += al(sizeof(int32_t) * (size_t)nb);
+    int32_t* offs = reinterpret_cast<int32_t*>(p);
+    p += al(sizeof(int32_t) * ((size_t)nb + 1));
+    int32_t* partials = reinterpret_cast<int32_t*>(p);
+
+    if (nb == 0) {
+        int rc = geo_fill_u64(reinterpret_cast<uint64_t*>(d_nchild), 0, 1, s);
+        return rc;
+    }
+    const unsigned g = grid_for(nb);
+    k_ref_nbr<<<g, 256, 0, s>>>(d, solid, nbr, flags);
+    k_ref_class<<<g, 256, 0, s>>>(nb, nbr, flags, cls);
+    k_ref_m1<<<g, 256, 0, s>>>(nb, nbr, cls, M, bclass);
+    for (int k = 1; k <= n_prop; k++) {
+        k_ref_prop<<<g, 256, 0, s>>>(nb, nbr, cls, M, Mn, k == 1 ? 1 : 0);
+        uint8_t* t = M;
+        M = Mn;
+        Mn = t;
+    }
+    k_ref_final<<<g, 256, 0, s>>>(nb, cls, M, refine, cnt);
+    GEO_LAUNCH_CHECK();
+    int rc = geo_scan_exclusive(cnt, offs, nb, partials, s);
+    if (rc != GEO_OK) return rc;
+    k_ref_emit<<<g, 256, 0, s>>>(d, refine, offs, child_map, child_bcoord, d_nchild);
+    GEO_LAUNCH_CHECK();
+    return GEO_OK;
+}

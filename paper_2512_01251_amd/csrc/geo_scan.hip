@@ -1,0 +1,152 @@
+// Device-wide exclusive scan of int32 counts and small fill kernels.
+#include "geo_internal.h"
+
+namespace {
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+// inclusive scan across the 64 lanes of a wave
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// exclusive scan across the block; returns the block total in *total
+__device__ __forceinline__ int block_excl_scan(int v, int* total) {
+    __shared__ int wsum[SCAN_THREADS / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int incl = wave_incl_scan(v);
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_THREADS / 64; i++) {
+        if (i < w) base += wsum[i];
+        tot += wsum[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + incl - v;
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_tile_sums(const int32_t* in, int64_t n, int32_t* partials) {
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        int64_t k = base + (int64_t)i * SCAN_THREADS + threadIdx.x;
+        if (k < n) s += in[k];
+    }
+    int tot;
+    block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// single workgroup: exclusive scan of the tile sums, total at partials[ntiles]
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_partials(int32_t* partials, int64_t ntiles) {
+    int carry = 0;
+    for (int64_t c0 = 0; c0 < ntiles; c0 += SCAN_TILE) {
+        int v[SCAN_ITEMS];
+        int s = 0;
+#pragma unroll
+        for (int i = 0; i < SCAN_ITEMS; i++) {
+            int64_t k = c0 + (int64_t)threadIdx.x * SCAN_ITEMS + i;
+            v[i] = k < ntiles ? partials[k] : 0;
+            s += v[i];
+        }
+        int tot;
+        int ex = block_excl_scan(s, &tot) + carry;
+#pragma unroll
+        for (int i = 0; i < SCAN_ITEMS; i++) {
+            int64_t k = c0 + (int64_t)threadIdx.x * SCAN_ITEMS + i;
+            if (k < ntiles) partials[k] = ex;
+            ex += v[i];
+        }
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[ntiles] = carry;
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_tiles(const int32_t* in, int32_t* out, int64_t n,
+                                                            const int32_t* partials, int64_t ntiles) {
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    int v[SCAN_ITEMS];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        int64_t k = base + (int64_t)threadIdx.x * SCAN_ITEMS + i;
+        v[i] = k < n ? in[k] : 0;
+        s += v[i];
+    }
+    int tot;
+    int ex = block_excl_scan(s, &tot) + partials[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        int64_t k = base + (int64_t)threadIdx.x * SCAN_ITEMS + i;
+        if (k < n) out[k] = ex;
+        ex += v[i];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = partials[ntiles];
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_u64(uint64_t* p, uint64_t v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+inline unsigned grid_for(int64_t n, int threads) {
+    int64_t g = (n + threads - 1) / threads;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+size_t geo_scan_partials_bytes(int64_t n) {
+    int64_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    return sizeof(int32_t) * (size_t)(ntiles + 1);
+}
+
+// out[0..n-1] = exclusive prefix sums of in, out[n] = total.  in and out must
+// not overlap.  partials: geo_scan_partials_bytes(n) bytes.
+int geo_scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* partials, hipStream_t s) {
+    int64_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (ntiles == 0) {
+        k_fill_i32<<<1, 64, 0, s>>>(out, 0, 1);
+        GEO_LAUNCH_CHECK();
+        return GEO_OK;
+    }
+    k_tile_sums<<<(unsigned)ntiles, SCAN_THREADS, 0, s>>>(in, n, partials);
+    k_scan_partials<<<1, SCAN_THREADS, 0, s>>>(partials, ntiles);
+    k_scan_tiles<<<(unsigned)ntiles, SCAN_THREADS, 0, s>>>(in, out, n, partials, ntiles);
+    GEO_LAUNCH_CHECK();
+    return GEO_OK;
+}
+
+int geo_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return GEO_OK;
+    k_fill_i32<<<grid_for(n, 256), 256, 0, s>>>(p, v, n);
+    GEO_LAUNCH_CHECK();
+    return GEO_OK;
+}
+
+int geo_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return GEO_OK;
+    k_fill_u64<<<grid_for(n, 256), 256, 0, s>>>(p, v, n);
+    GEO_LAUNCH_CHECK();
+    return GEO_OK;
+}

@@ -1,0 +1,190 @@
+"""CPU checks of libgeo: exported C-ABI, host-side argument validation, and
+the library's own exact predicates and filters compiled for the host.
+
+No GPU is needed: the argument checks return before any HIP call, and the
+predicate helpers are __host__ __device__ code built into a host-only
+harness (tests/host_predicates.hip).
+"""
+import ctypes as C
+import os
+import re
+import subprocess
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "geo.h")).read()
+    return sorted(set(re.findall(r"^\w[\w\s\*]*?\b(geo_\w+)\s*\(", txt, re.M)))
+
+
+@pytest.fixture(scope="module")
+def geo():
+    import paper_2512_01251_amd as g
+    return g
+
+
+def test_library_exports_every_declared_symbol(geo):
+    names = _header_functions()
+    assert len(names) >= 9
+    L = geo.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(geo.EXPORTS)
+
+
+def test_version_and_nprop(geo):
+    import oracle
+    assert "gfx950" in geo.geo_version()
+    for d in [0.0, 0.5, 2.0, 4 * 2 ** 0.5, 5.65, 5.66, 11.31, 11.32, 17.0, 100.0]:
+        assert geo.geo_nprop(d) == oracle.n_prop(d), d
+
+
+def test_workspace_sizes_monotone(geo):
+    a = geo.geo_workspace_size(geo.GEO_CALL_BINS_ROWS, 1000, 100)
+    b = geo.geo_workspace_size(geo.GEO_CALL_BINS_ROWS, 1000, 10000)
+    assert 0 < a < b
+    assert geo.geo_workspace_size(geo.GEO_CALL_REFINE, 100, 0) >= 26 * 4 * 100
+    assert geo.geo_workspace_size(99, 10, 10) == 0
+
+
+def test_bad_arguments_are_rejected_on_the_host(geo):
+    L = geo.lib()
+    lv = geo.geo_level()
+    for a in range(3):
+        lv.n0[a] = 30          # not a multiple of 4
+    lv.level = 0
+    lv.nblocks = 0
+    mesh = geo.geo_mesh(0, 0, geo.GEO_F32, None, None)
+    bins = geo.geo_bins(geo.GEO_BINS_ROWS, 0, None, None, 0, None)
+    rc = L.geo_build_bins(C.byref(mesh), C.byref(lv), 0, 0, C.byref(bins), None, None, 0, None)
+    assert rc == geo.GEO_ERR_ARG
+    n0 = (C.c_int32 * 3)(30, 32, 32)
+    assert L.geo_level0_blocks(n0, None, None) == geo.GEO_ERR_ARG
+    for a in range(3):
+        lv.n0[a] = 32
+    lv.level = 13               # beyond GEO_MAX_LEVELS
+    assert L.geo_voxelize(C.byref(lv), C.byref(bins), None, None) == geo.GEO_ERR_ARG
+    lv.level = 11               # 32 * 2^11 > GEO_MAX_RES
+    assert L.geo_voxelize(C.byref(lv), C.byref(bins), None, None) == geo.GEO_ERR_ARG
+    lv.level = 0
+    assert L.geo_cutlinks(C.byref(mesh), C.byref(lv), C.byref(bins), C.byref(bins), 15, 0, None, 0,
+                          None, None, None, None, None, None, None, 0, None) == geo.GEO_ERR_ARG
+    assert L.geo_refine_flags(C.byref(lv), None, -1, None, None, None, None, None, None, 0,
+                              None) == geo.GEO_ERR_ARG
+
+
+# ----------------------------------------------------------------------------
+# the library's exact predicates, built for the host
+# ----------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def hp(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("hp") / "hp.so")
+    src = os.path.join(ROOT, "tests", "host_predicates.hip")
+    cmd = ["/opt/rocm/bin/hipcc", "-O2", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(ROOT, "paper_2512_01251_amd", "csrc"),
+           src, "-o", out]
+    subprocess.run(cmd, check=True, capture_output=True)
+    L = C.CDLL(out)
+    d = C.c_double
+    P = C.c_void_p
+    for f in ("hp_orient2d_exact", "hp_orient2d_filter_f64", "hp_orient2d_filter_f32"):
+        getattr(L, f).argtypes = [d] * 6
+    for f in ("hp_orient3d_exact", "hp_orient3d_filter_f64", "hp_orient3d_filter_f32"):
+        getattr(L, f).argtypes = [P] * 4
+    return L
+
+
+def sgn(x):
+    return (x > 0) - (x < 0)
+
+
+def o2_ref(a, b, c):
+    ax, ay, bx, by, cx, cy = map(F, (a[0], a[1], b[0], b[1], c[0], c[1]))
+    return sgn((ax - cx) * (by - cy) - (ay - cy) * (bx - cx))
+
+
+def o3_ref(a, b, c, d):
+    A = [[F(float(p[k])) - F(float(d[k])) for k in range(3)] for p in (a, b, c)]
+    return sgn(A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1])
+               - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0])
+               + A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]))
+
+
+def _pts3(rng, n, scale):
+    """Random and constructed near-degenerate quadruples within the library's
+    coordinate contract (multiples of 2^-64, |x| < 2^15)."""
+    out = []
+    for _ in range(n):
+        kind = rng.integers(5)
+        a, b, c = (rng.uniform(-scale, scale, 3) for _ in range(3))
+        if kind == 0:
+            d = rng.uniform(-scale, scale, 3)
+        elif kind == 1:
+            a, b, c = (np.round(p * 64) / 64 for p in (a, b, c))
+            u, v = rng.integers(-8, 9, 2) / 8.0
+            d = a + u * (b - a) + v * (c - a)
+        elif kind == 2:
+            a, b, c = (np.round(p * 64) / 64 for p in (a, b, c))
+            d = a + 0.25 * (b - a) + 0.5 * (c - a)
+            k = rng.integers(3)
+            d[k] = np.nextafter(d[k], np.inf if rng.integers(2) else -np.inf)
+        elif kind == 3:
+            u, v = rng.uniform(size=2)
+            d = a + u * (b - a) + v * (c - a)
+        else:  # integer lattice point against a triangle through lattice points
+            a, b, c = (np.round(p) for p in (a, b, c))
+            d = np.round(rng.uniform(-scale, scale, 3))
+        # the contract: coordinates are multiples of 2^-64 (true of every
+        # local coordinate the kernels form from vertices >= 2^-12)
+        snap = lambda p: np.ldexp(np.round(np.ldexp(p, 52)), -52)
+        out.append(tuple(snap(p) for p in (a, b, c, d)))
+    return out
+
+
+@pytest.mark.parametrize("scale", [1.0, 300.0, 30000.0])
+def test_library_exact_orient3d_matches_fractions(hp, scale):
+    rng = np.random.default_rng(int(scale))
+    P = lambda x: np.ascontiguousarray(x, dtype=np.float64).ctypes.data_as(C.c_void_p)
+    zeros = 0
+    for (a, b, c, d) in _pts3(rng, 2000, scale):
+        ref = o3_ref(a, b, c, d)
+        zeros += ref == 0
+        arr = [np.ascontiguousarray(x, dtype=np.float64) for x in (a, b, c, d)]
+        ptr = [x.ctypes.data_as(C.c_void_p) for x in arr]
+        assert hp.hp_orient3d_exact(*ptr) == ref
+        f64 = hp.hp_orient3d_filter_f64(*ptr)
+        assert f64 in (0, ref)
+        f32 = hp.hp_orient3d_filter_f32(*ptr)
+        assert f32 in (0, ref)
+    assert zeros > 200
+
+
+def test_library_exact_orient2d_matches_fractions(hp):
+    rng = np.random.default_rng(5)
+    for (a, b, c, _) in _pts3(rng, 3000, 500.0):
+        a2, b2, c2 = a[:2], b[:2], c[:2]
+        if rng.integers(2):
+            c2 = a2 + rng.integers(-4, 5) / 4.0 * (b2 - a2)
+        ref = o2_ref(a2, b2, c2)
+        args = [float(x) for x in (*a2, *b2, *c2)]
+        assert hp.hp_orient2d_exact(*args) == ref
+        assert hp.hp_orient2d_filter_f64(*args) in (0, ref)
+        assert hp.hp_orient2d_filter_f32(*args) in (0, ref)
+
+
+def test_float_filters_certify_most_random_cases(hp):
+    rng = np.random.default_rng(6)
+    cert32 = cert64 = 0
+    for _ in range(2000):
+        a, b, c, d = (np.ascontiguousarray(rng.uniform(0, 8, 3)) for _ in range(4))
+        ptr = [x.ctypes.data_as(C.c_void_p) for x in (a, b, c, d)]
+        cert64 += hp.hp_orient3d_filter_f64(*ptr) != 0
+        cert32 += hp.hp_orient3d_filter_f32(*ptr) != 0
+    assert cert64 == 2000 and cert32 > 1900
