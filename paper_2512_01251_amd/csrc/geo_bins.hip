@@ -277,7 +277,8 @@ __device__ void row_events(const DevMesh& m, const RowTri<R>& T, double s, int m
         }
         if (chain_o2_yz<R>(m, T, s, bi, (bi + 1) % 3, py, pz, st) != 0) return;
         const int pw = drop == 1 ? py : pz;  // coordinate kept beside x
-        int first = -1, last = -2;
+        bool found = false;
+        int first = 0, last = 0;  // local indices; may be negative
         const int lo = (int)ceil((double)xmn), hi = (int)floor((double)xmx);
         for (int c = lo; c <= hi; c++) {
             bool in = true;
@@ -286,13 +287,14 @@ __device__ void row_events(const DevMesh& m, const RowTri<R>& T, double s, int m
                 if (r * areaSign < 0) in = false;
             }
             if (in) {
-                if (first < 0) first = c;
+                if (!found) first = c;
+                found = true;
                 last = c;
-            } else if (first >= 0) {
+            } else if (found) {
                 break;  // convex: the inside centres are contiguous
             }
         }
-        if (first >= 0) {
+        if (found) {
             int gl = first + T.o[0], gh = last + T.o[0];
             gl = gl < 0 ? 0 : gl;
             gh = gh > nx - 1 ? nx - 1 : gh;
