@@ -68,9 +68,11 @@ enum { GEO_CALL_BINS_ROWS = 0, GEO_CALL_BINS_LINKS = 1, GEO_CALL_REFINE = 2, GEO
 enum {
     GEO_STAT_F32_TO_F64 = 0, /* float32 sign tests re-evaluated in float64          */
     GEO_STAT_EXACT = 1,      /* float64 sign tests resolved by exact arithmetic     */
-    GEO_STAT_Q_F64 = 2,      /* q values recomputed in float64 (ill-conditioned)    */
+    GEO_STAT_LINKS_EXACT = 2, /* links whose nearest hit was redone exactly          */
     GEO_STAT_CONTRACT = 3,   /* vertex coordinates outside the documented range     */
-    GEO_NSTATS = 4
+    GEO_STAT_STAGED = 4,     /* candidate triangles staged by the q kernel          */
+    GEO_STAT_PAIRS = 5,      /* (link, candidate) pairs passing the box test        */
+    GEO_NSTATS = 6
 };
 
 #define GEO_MAX_LEVELS 12
@@ -179,9 +181,10 @@ int geo_refine_flags(const geo_level* lv, const uint64_t* solid, int32_t n_prop,
 /*
  * Cut links of level L (Methodology, "Boundary Cell Identification", "Memory
  * Allocations for Boundary Cells", "Link-Length Computation", Eq. 2).
- *   link_mask[b*64+t] bit k: cell t of block b is fluid and the same-level
- *     centre x + h c_k is solid (classified from the ROWS bins, also where
- *     that centre's block does not exist; centres outside the domain are fluid);
+ *   link_mask[b*64+t] bit k (optional output, may be NULL): cell t of block b
+ *     is fluid and the same-level centre x + h c_k is solid (classified from
+ *     the ROWS bins, also where that centre's block does not exist; centres
+ *     outside the domain are fluid);
  *   the table lists every set bit in the order (block, t, k):
  *     link_cell = b*64 + t, link_dir = k,
  *     link_q = min t in (0,1] with x + t h c_k on the surface,

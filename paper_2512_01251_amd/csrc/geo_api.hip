@@ -5,7 +5,7 @@
 #include "geo_internal.h"
 
 size_t geo_refine_ws_bytes(int64_t nb);
-size_t geo_cutlinks_ws_bytes(int64_t nb);
+size_t geo_cutlinks_ws_bytes(int64_t nb, int64_t cap);
 
 namespace {
 
@@ -60,7 +60,7 @@ size_t geo_workspace_size(int32_t call, int64_t nkeys, int64_t cap) {
         case GEO_CALL_BINS_ROWS:
         case GEO_CALL_BINS_LINKS: return bins_ws_bytes(nkeys, cap);
         case GEO_CALL_REFINE: return geo_refine_ws_bytes(nkeys);
-        case GEO_CALL_CUTLINKS: return geo_cutlinks_ws_bytes(nkeys);
+        case GEO_CALL_CUTLINKS: return geo_cutlinks_ws_bytes(nkeys, cap);
         default: return 0;
     }
 }
@@ -148,9 +148,10 @@ int geo_cutlinks(const geo_mesh* mesh, const geo_level* lv, const geo_bins* rows
         return GEO_ERR_ARG;
     if (lattice != 19 && lattice != 27) return GEO_ERR_ARG;
     if (precision != GEO_PREC_F64 && precision != GEO_PREC_F32_FALLBACK) return GEO_ERR_ARG;
-    if (cap < 0 || !d_nlinks || (lv->nblocks > 0 && !link_mask)) return GEO_ERR_ARG;
+    if (cap < 0 || !d_nlinks) return GEO_ERR_ARG;
     if (cap > 0 && (!link_cell || !link_dir || !link_q || !link_tri)) return GEO_ERR_ARG;
-    if (ws_bytes < geo_cutlinks_ws_bytes(lv->nblocks) || (!ws && ws_bytes)) return GEO_ERR_WORKSPACE;
+    if (mesh->nt >= (1 << 27)) return GEO_ERR_ARG;  // hit keys hold 27-bit triangle ids
+    if (ws_bytes < geo_cutlinks_ws_bytes(lv->nblocks, cap) || (!ws && ws_bytes)) return GEO_ERR_WORKSPACE;
     return launch_cutlinks(dev_mesh(mesh), dev_level(lv), rows, links, lattice, precision, link_mask, cap, d_nlinks,
                            link_cell, link_dir, link_q, link_tri, d_stats, ws, ws_bytes, (hipStream_t)stream);
 }

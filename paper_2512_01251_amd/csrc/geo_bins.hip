@@ -17,23 +17,48 @@
 namespace {
 
 // ------------------------------------------------------------------------
-// wave-aggregated append of (key, value) pairs
+// Append of (key, value) pairs.  Each workgroup is one wave; pairs are staged
+// in an LDS buffer and flushed with one global reservation per flush (a
+// global counter touched once per wave-iteration would serialise at L2).
+// The per-key counts are incremented at flush time.
 // ------------------------------------------------------------------------
-__device__ __forceinline__ void wave_append(bool has, int key, int32_t val, int2* pairs, int64_t cap,
-                                            int64_t* d_count, int32_t* cnt) {
-    const unsigned long long mask = __ballot(has);
-    if (mask == 0ull) return;
-    const int lane = __lane_id();
-    const int leader = __ffsll((long long)mask) - 1;
-    unsigned long long base = 0;
-    if (lane == leader) base = atomicAdd((unsigned long long*)d_count, (unsigned long long)__popcll(mask));
-    base = __shfl(base, leader, 64);
-    if (has) {
-        const unsigned long long pos = base + __popcll(mask & ((1ull << lane) - 1ull));
-        if (pos < (unsigned long long)cap) pairs[pos] = make_int2(key, val);
-        atomicAdd(&cnt[key], 1);
+constexpr int APP_BUF = 2048;
+
+struct Appender {
+    int2* buf;       // LDS [APP_BUF]
+    int n;           // pairs staged (identical in every lane)
+    int2* pairs;
+    int64_t cap;
+    int64_t* d_count;
+    int32_t* cnt;
+
+    __device__ __forceinline__ void flush() {
+        if (n == 0) return;
+        __syncthreads();
+        unsigned long long base = 0;
+        if (threadIdx.x == 0) base = atomicAdd((unsigned long long*)d_count, (unsigned long long)n);
+        base = __shfl(base, 0, 64);
+        for (int i = threadIdx.x; i < n; i += 64) {
+            const int2 p = buf[i];
+            const unsigned long long pos = base + (unsigned long long)i;
+            if (pos < (unsigned long long)cap) pairs[pos] = p;
+            atomicAdd(&cnt[p.x], 1);
+        }
+        __syncthreads();
+        n = 0;
     }
-}
+    __device__ __forceinline__ void add(bool has, int key, int32_t val) {
+        const unsigned long long mask = __ballot(has);
+        if (mask == 0ull) return;
+        const int k = __popcll(mask);
+        if (n + k > APP_BUF) flush();
+        if (has) {
+            const int lane = __lane_id();
+            buf[n + __popcll(mask & ((1ull << lane) - 1ull))] = make_int2(key, val);
+        }
+        n += k;
+    }
+};
 
 // ------------------------------------------------------------------------
 // per-triangle local frame for the row pass
@@ -307,8 +332,10 @@ __device__ void row_events(const DevMesh& m, const RowTri<R>& T, double s, int m
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_rows_pass1(DevMesh m, DevLevel d, int32_t* cnt, int2* pairs,
-                                                    int64_t cap, int64_t* d_count, uint64_t* stats) {
+__global__ void __launch_bounds__(64) k_rows_pass1(DevMesh m, DevLevel d, int32_t* cnt, int2* pairs,
+                                                   int64_t cap, int64_t* d_count, uint64_t* stats) {
+    __shared__ int2 sbuf[APP_BUF];
+    Appender app{sbuf, 0, pairs, cap, d_count, cnt};
     const int L = d.level;
     const int nx = d.n0[0] << L, ny = d.n0[1] << L, nz = d.n0[2] << L;
     const double s = ldexp(1.0, L);
@@ -345,10 +372,11 @@ __global__ void __launch_bounds__(256) k_rows_pass1(DevMesh m, DevLevel d, int32
                 key = j + ny * k;
                 row_events<R>(m, T, s, mode, drop, areaSign, j, k, nx, st, h0, e0, h1, e1);
             }
-            wave_append(h0, key, e0, pairs, cap, d_count, cnt);
-            wave_append(h1, key, e1, pairs, cap, d_count, cnt);
+            app.add(h0, key, e0);
+            app.add(h1, key, e1);
         }
     }
+    app.flush();
     if (stats) {
         if constexpr (std::is_same<R, float>::value) wave_count(&stats[GEO_STAT_F32_TO_F64], st.fb);
         wave_count(&stats[GEO_STAT_EXACT], st.ex);
@@ -401,8 +429,10 @@ __device__ bool tri_box_overlap(const double* c, double hs, const double v0in[3]
     return true;
 }
 
-__global__ void __launch_bounds__(256) k_links_pass1(DevMesh m, DevLevel d, int32_t* cnt, int2* pairs,
-                                                     int64_t cap, int64_t* d_count) {
+__global__ void __launch_bounds__(64) k_links_pass1(DevMesh m, DevLevel d, int32_t* cnt, int2* pairs,
+                                                    int64_t cap, int64_t* d_count) {
+    __shared__ int2 sbuf[APP_BUF];
+    Appender app{sbuf, 0, pairs, cap, d_count, cnt};
     const int L = d.level;
     const double h = ldexp(1.0, -L), bw = 4.0 * h;
     const int nbx = (d.n0[0] >> 2) << L, nby = (d.n0[1] >> 2) << L, nbz = (d.n0[2] >> 2) << L;
@@ -411,16 +441,29 @@ __global__ void __launch_bounds__(256) k_links_pass1(DevMesh m, DevLevel d, int3
         const int64_t t = base + threadIdx.x;
         double v[3][3];
         int lo[3] = {0, 0, 0}, hi[3] = {-1, -1, -1};
-        if (t < m.nt) {
+        bool live = t < m.nt;
+        if (live) {
             for (int i = 0; i < 3; i++) {
                 const int vid = m.tris[3 * t + i];
                 for (int a = 0; a < 3; a++) v[i][a] = load_coord(m, vid, a);
             }
+            // zero-area triangles never meet a segment: exact test (all three
+            // coordinate-plane projections have zero area)
+            if (orient2d_filter<double>(v[0][1], v[0][2], v[1][1], v[1][2], v[2][1], v[2][2], 0.0) == 0 &&
+                orient2d_filter<double>(v[0][2], v[0][0], v[1][2], v[1][0], v[2][2], v[2][0], 0.0) == 0 &&
+                orient2d_filter<double>(v[0][0], v[0][1], v[1][0], v[1][1], v[2][0], v[2][1], 0.0) == 0 &&
+                orient2d_exact(v[0][1], v[0][2], v[1][1], v[1][2], v[2][1], v[2][2]) == 0 &&
+                orient2d_exact(v[0][2], v[0][0], v[1][2], v[1][0], v[2][2], v[2][0]) == 0 &&
+                orient2d_exact(v[0][0], v[0][1], v[1][0], v[1][1], v[2][0], v[2][1]) == 0)
+                live = false;
+        }
+        if (live) {
             const int nb[3] = {nbx, nby, nbz};
             for (int a = 0; a < 3; a++) {
                 const double mn = fmin(v[0][a], fmin(v[1][a], v[2][a])), mx = fmax(v[0][a], fmax(v[1][a], v[2][a]));
-                lo[a] = (int)floor((mn - 2.0 * h) / bw);
-                hi[a] = (int)floor((mx + 2.0 * h) / bw);
+                // block b's widened box is [4bh - h, 4bh + 5h]
+                lo[a] = (int)ceil((mn - 5.0 * h) / bw);
+                hi[a] = (int)floor((mx + h) / bw);
                 lo[a] = lo[a] < 0 ? 0 : lo[a];
                 hi[a] = hi[a] > nb[a] - 1 ? nb[a] - 1 : hi[a];
             }
@@ -441,9 +484,10 @@ __global__ void __launch_bounds__(256) k_links_pass1(DevMesh m, DevLevel d, int3
                     key = idx;
                 }
             }
-            wave_append(has, key, (int32_t)t, pairs, cap, d_count, cnt);
+            app.add(has, key, (int32_t)t);
         }
     }
+    app.flush();
 }
 
 __global__ void k_bins_scatter(const int2* pairs, int64_t cap, const int64_t* d_count, const int32_t* off,
@@ -481,11 +525,11 @@ inline unsigned grid_for(int64_t n, int threads, int64_t maxg = 1 << 16) {
 int launch_rows_pass1(const DevMesh& m, const DevLevel& d, int precision, int32_t* cnt, int2* pairs,
                       int64_t cap, int64_t* d_count, uint64_t* d_stats, hipStream_t s) {
     if (m.nt == 0) return GEO_OK;
-    const unsigned g = grid_for(m.nt, 256);
+    const unsigned g = grid_for(m.nt, 64, 16384);
     if (precision == GEO_PREC_F32_FALLBACK)
-        k_rows_pass1<float><<<g, 256, 0, s>>>(m, d, cnt, pairs, cap, d_count, d_stats);
+        k_rows_pass1<float><<<g, 64, 0, s>>>(m, d, cnt, pairs, cap, d_count, d_stats);
     else
-        k_rows_pass1<double><<<g, 256, 0, s>>>(m, d, cnt, pairs, cap, d_count, d_stats);
+        k_rows_pass1<double><<<g, 64, 0, s>>>(m, d, cnt, pairs, cap, d_count, d_stats);
     GEO_LAUNCH_CHECK();
     return GEO_OK;
 }
@@ -493,7 +537,7 @@ int launch_rows_pass1(const DevMesh& m, const DevLevel& d, int precision, int32_
 int launch_links_pass1(const DevMesh& m, const DevLevel& d, int32_t* cnt, int2* pairs, int64_t cap,
                        int64_t* d_count, hipStream_t s) {
     if (m.nt == 0) return GEO_OK;
-    k_links_pass1<<<grid_for(m.nt, 256), 256, 0, s>>>(m, d, cnt, pairs, cap, d_count);
+    k_links_pass1<<<grid_for(m.nt, 64, 16384), 64, 0, s>>>(m, d, cnt, pairs, cap, d_count);
     GEO_LAUNCH_CHECK();
     return GEO_OK;
 }

@@ -8,12 +8,17 @@
 //             reduces the block's link count.
 //  scan       block counts -> offsets: the table is laid out in the order
 //             (block, t, k) without atomics (scan-ordered compaction).
-//  k_cl_q     one wave per block: the block's candidate triangles (LINKS bins)
-//             are staged in LDS with certified plane coefficients; lane i
-//             takes link i, tests it against every candidate and keeps the
-//             nearest hit (the paper's minimum over binned faces).  Signs that
-//             the fast precision cannot certify are recomputed in float64 and
-//             then exactly.
+//  k_cl_q     tasks of (64 links x 64 candidates) of a block: the candidates
+//             (LINKS bins) are staged in LDS with certified plane coefficients;
+//             box tests list the (link, candidate) pairs worth testing, the
+//             pairs are flattened over the wave and tested with sign filters in
+//             the form's precision, the hit parameter comes from the float64
+//             plane, and each link keeps its nearest hit (the paper's minimum
+//             over binned faces) through a 64-bit atomic min on a packed
+//             (t, triangle) key.  A link with a pair whose signs the filters
+//             cannot certify is queued.
+//  k_cl_fix   one wave per queued link: exact tests against all candidates.
+//  k_cl_final keys -> q and hit triangle.
 #include <type_traits>
 
 #include "geo_internal.h"
@@ -67,39 +72,45 @@ __device__ __forceinline__ unsigned halo_bits(const int32_t* off, const int32_t*
     return r;
 }
 
-__global__ void __launch_bounds__(64) k_cl_mask(DevLevel d, const int32_t* off, const int32_t* val, int64_t cap,
-                                                int lattice, uint32_t* link_mask, int32_t* blk_cnt) {
-    __shared__ unsigned halo[36];
+// link masks of block b: lanes 0..35 classify the 36 halo row lines into
+// LDS, then lane t forms the mask of cell t (0 for solid cells)
+__device__ __forceinline__ uint32_t block_link_mask(const DevLevel& d, const int32_t* off, const int32_t* val,
+                                                    int64_t cap, uint32_t dirs, int64_t b, unsigned* halo) {
     const int L = d.level;
     const int nx = d.n0[0] << L, ny = d.n0[1] << L, nz = d.n0[2] << L;
     const int lane = threadIdx.x;
+    const int bx = d.bcoord[3 * b], by = d.bcoord[3 * b + 1], bz = d.bcoord[3 * b + 2];
+    __syncthreads();
+    if (lane < 36) {
+        const int J = lane % 6 - 1, K = lane / 6 - 1;
+        const int j = 4 * by + J, k = 4 * bz + K;
+        unsigned bits = 0;
+        if (j >= 0 && j < ny && k >= 0 && k < nz)
+            bits = halo_bits(off, val, cap, (int64_t)j + (int64_t)ny * k, 4 * bx - 1, nx);
+        halo[lane] = bits;
+    }
+    __syncthreads();
+    const int I = lane & 3, J = (lane >> 2) & 3, K = lane >> 4;
+    // 27-bit neighbourhood word, bit (cx+1) + 3 (cy+1) + 9 (cz+1)
+    uint32_t nb = 0;
+#pragma unroll
+    for (int dz = 0; dz < 3; dz++)
+#pragma unroll
+        for (int dy = 0; dy < 3; dy++) nb |= ((halo[(J + dy) + 6 * (K + dz)] >> I) & 7u) << (3 * dy + 9 * dz);
+    return ((nb >> 13) & 1u) ? 0u : (nb & dirs);
+}
+
+__global__ void __launch_bounds__(64) k_cl_mask(DevLevel d, const int32_t* off, const int32_t* val, int64_t cap,
+                                                int lattice, uint32_t* link_mask, int32_t* blk_cnt) {
+    __shared__ unsigned halo[36];
     const uint32_t dirs = lattice_dirs(lattice);
     for (int64_t b = blockIdx.x; b < d.nblocks; b += gridDim.x) {
-        const int bx = d.bcoord[3 * b], by = d.bcoord[3 * b + 1], bz = d.bcoord[3 * b + 2];
-        if (lane < 36) {
-            const int J = lane % 6 - 1, K = lane / 6 - 1;
-            const int j = 4 * by + J, k = 4 * bz + K;
-            unsigned bits = 0;
-            if (j >= 0 && j < ny && k >= 0 && k < nz) bits = halo_bits(off, val, cap, (int64_t)j + (int64_t)ny * k, 4 * bx - 1, nx);
-            halo[lane] = bits;
-        }
-        __syncthreads();
-        const int I = lane & 3, J = (lane >> 2) & 3, K = lane >> 4;
-        uint32_t m = 0;
-        if (!((halo[(J + 1) + 6 * (K + 1)] >> (I + 1)) & 1u)) {
-            for (int k = 0; k < 27; k++) {
-                if (!((dirs >> k) & 1u)) continue;
-                int cx, cy, cz;
-                dirvec(k, cx, cy, cz);
-                if ((halo[(J + 1 + cy) + 6 * (K + 1 + cz)] >> (I + 1 + cx)) & 1u) m |= 1u << k;
-            }
-        }
-        link_mask[64 * b + lane] = m;
+        const uint32_t m = block_link_mask(d, off, val, cap, dirs, b, halo);
+        if (link_mask) link_mask[64 * b + threadIdx.x] = m;
         int c = __popc(m);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-        if (lane == 0) blk_cnt[b] = c;
-        __syncthreads();
+        if (threadIdx.x == 0) blk_cnt[b] = c;
     }
 }
 
@@ -110,7 +121,7 @@ __global__ void k_cl_total(const int32_t* blk_off, int64_t nb, int64_t* d_nlinks
 // ------------------------------------------------------------------------
 // candidate records
 // ------------------------------------------------------------------------
-enum { C_SKIP = 1, C_SLOW = 2 };
+enum { C_SLOW = 2 };
 
 template <typename R>
 struct Cand {
@@ -119,10 +130,15 @@ struct Cand {
     R off;          // n . a
     R bound;        // |(off - n.P) - orient3d(a,b,c,P)| <= bound for P in [-1,4]^3
     R delta;        // rounding bound of v
-    double n64[3];  // float64 plane for refining t
+    double n64[3];  // float64 plane for the hit parameter
     double off64;
     int tri;
-    int flags;
+};
+
+// bounding box of a staged candidate (float, rounded outward) with flags in lo.w
+struct CBox {
+    float4 lo;  // xyz: lower corner, w: flags (as float)
+    float4 hi;
 };
 
 // scaled global coordinate v 2^L - 1/2 (exact)
@@ -130,14 +146,27 @@ __device__ __forceinline__ void vert_scaled(const DevMesh& m, int vid, double s,
     for (int a = 0; a < 3; a++) g[a] = load_coord(m, vid, a) * s - 0.5;
 }
 
+__device__ __forceinline__ float down_f(double x) {
+    float f = (float)x;
+    return (double)f > x ? nextafterf(f, -1e30f) : f;
+}
+__device__ __forceinline__ float up_f(double x) {
+    float f = (float)x;
+    return (double)f < x ? nextafterf(f, 1e30f) : f;
+}
+
+// Stage one candidate: local float64 coordinates (exact unless flagged slow),
+// certified plane coefficients in R, float64 plane, float box.
 template <typename R>
-__device__ void stage_cand(const DevMesh& m, int L, int tri, const int b0[3], Cand<R>& C) {
+__device__ void stage_cand(const DevMesh& m, int L, int tri, const int b0[3], Cand<R>& C, CBox& B) {
     const double s = ldexp(1.0, L);
     double v[3][3];
     bool exact = true;
+#pragma unroll
     for (int i = 0; i < 3; i++) {
         double g[3];
         vert_scaled(m, m.tris[3 * (int64_t)tri + i], s, g);
+#pragma unroll
         for (int a = 0; a < 3; a++) {
             const double o = (double)b0[a];
             const double sum = g[a] - o;
@@ -148,7 +177,7 @@ __device__ void stage_cand(const DevMesh& m, int L, int tri, const int b0[3], Ca
         }
     }
     C.tri = tri;
-    C.flags = exact ? 0 : C_SLOW;
+    int flags = exact ? 0 : C_SLOW;
     const double e1[3] = {v[1][0] - v[0][0], v[1][1] - v[0][1], v[1][2] - v[0][2]};
     const double e2[3] = {v[2][0] - v[0][0], v[2][1] - v[0][1], v[2][2] - v[0][2]};
     double n[3], perm[3];
@@ -159,62 +188,72 @@ __device__ void stage_cand(const DevMesh& m, int L, int tri, const int b0[3], Ca
     perm[1] = fabs(e1[2] * e2[0]) + fabs(e1[0] * e2[2]);
     perm[2] = fabs(e1[0] * e2[1]) + fabs(e1[1] * e2[0]);
     const double u64 = 1.1102230246251565e-16;
-    // degenerate (zero-area) triangles never meet a segment
-    if (fabs(n[0]) <= 5 * u64 * perm[0] && fabs(n[1]) <= 5 * u64 * perm[1] && fabs(n[2]) <= 5 * u64 * perm[2]) {
-        double g[3][3];
-        for (int i = 0; i < 3; i++) vert_scaled(m, m.tris[3 * (int64_t)tri + i], s, g[i]);
-        if (orient2d_exact(g[0][1], g[0][2], g[1][1], g[1][2], g[2][1], g[2][2]) == 0 &&
-            orient2d_exact(g[0][2], g[0][0], g[1][2], g[1][0], g[2][2], g[2][0]) == 0 &&
-            orient2d_exact(g[0][0], g[0][1], g[1][0], g[1][1], g[2][0], g[2][1]) == 0)
-            C.flags |= C_SKIP;
-    }
+    // possibly zero-area: decided exactly by the deferred exact pass
+    if (fabs(n[0]) <= 5 * u64 * perm[0] && fabs(n[1]) <= 5 * u64 * perm[1] && fabs(n[2]) <= 5 * u64 * perm[2])
+        flags |= C_SLOW;
     const double off = n[0] * v[0][0] + n[1] * v[0][1] + n[2] * v[0][2];
-    double en[3], sna = 0, n1 = 0, ena = 0;
+    double sna = 0, n1 = 0, ena = 0;
+#pragma unroll
     for (int a = 0; a < 3; a++) {
-        en[a] = 5 * u64 * perm[a];
         sna += fabs(n[a] * v[0][a]);
         n1 += fabs(n[a]);
-        ena += en[a] * (fabs(v[0][a]) + 4.0);
+        ena += 5 * u64 * perm[a] * (fabs(v[0][a]) + 4.0);
     }
+#pragma unroll
     for (int a = 0; a < 3; a++) C.n64[a] = n[a];
     C.off64 = off;
-    double bound;
     if constexpr (std::is_same<R, float>::value) {
         const double u32 = 5.9604644775390625e-8;
         float n32[3];
+#pragma unroll
         for (int a = 0; a < 3; a++) n32[a] = (float)n[a];
         const float off32 = (float)off;
-        double n321 = fabs((double)n32[0]) + fabs((double)n32[1]) + fabs((double)n32[2]);
-        bound = u32 * fabs(off) + 3.01 * u64 * sna + ena + 4 * u32 * n1 + 4.01 * u32 * (fabs((double)off32) + 4 * n321);
+        const double n321 = fabs((double)n32[0]) + fabs((double)n32[1]) + fabs((double)n32[2]);
+        double bound = u32 * fabs(off) + 3.01 * u64 * sna + ena + 4 * u32 * n1 + 4.01 * u32 * (fabs((double)off32) + 4 * n321);
         bound = bound * 1.01 + 1e-30;
+#pragma unroll
         for (int a = 0; a < 3; a++) C.n[a] = n32[a];
         C.off = off32;
-        float bf = (float)bound;
-        if ((double)bf < bound) bf = nextafterf(bf, 1e30f);
-        C.bound = bf;
+        C.bound = up_f(bound);
         double dl = 0;
+#pragma unroll
         for (int i = 0; i < 3; i++)
+#pragma unroll
             for (int a = 0; a < 3; a++) {
                 C.v[i][a] = (float)v[i][a];
                 dl = fmax(dl, fabs((double)C.v[i][a] - v[i][a]));
             }
-        float df = (float)dl;
-        if ((double)df < dl) df = nextafterf(df, 1e30f);
-        C.delta = df;
+        C.delta = up_f(dl);
     } else {
-        bound = 3.01 * u64 * sna + ena + 4.01 * u64 * (fabs(off) + 4 * n1);
+        double bound = 3.01 * u64 * sna + ena + 4.01 * u64 * (fabs(off) + 4 * n1);
         bound = bound * 1.01 + 1e-300;
+#pragma unroll
         for (int a = 0; a < 3; a++) C.n[a] = n[a];
         C.off = off;
         C.bound = bound;
+#pragma unroll
         for (int i = 0; i < 3; i++)
+#pragma unroll
             for (int a = 0; a < 3; a++) C.v[i][a] = v[i][a];
         C.delta = 0;
     }
+    float lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        lo[a] = down_f(fmin(v[0][a], fmin(v[1][a], v[2][a])));
+        hi[a] = up_f(fmax(v[0][a], fmax(v[1][a], v[2][a])));
+    }
+    // inexact local coordinates: no box rejection for this candidate
+    if (!exact) {
+#pragma unroll
+        for (int a = 0; a < 3; a++) { lo[a] = -1e30f; hi[a] = 1e30f; }
+    }
+    B.lo = make_float4(lo[0], lo[1], lo[2], (float)flags);
+    B.hi = make_float4(hi[0], hi[1], hi[2], 0.0f);
 }
 
 struct QStats {
-    unsigned fb = 0, ex = 0, tq = 0;
+    unsigned fb = 0, ex = 0, tq = 0, staged = 0, pairs = 0;
 };
 
 // sign of orient3d with float64 filter then exact arithmetic
@@ -236,6 +275,7 @@ __device__ __forceinline__ int o2_sign64(double ax, double ay, double bx, double
 
 // axis dropped for in-plane 2D tests: one with a non-zero projected area
 __device__ int drop_axis(const double* A, const double* B, const double* C, int& area, QStats& st) {
+#pragma unroll
     for (int k = 0; k < 3; k++) {
         const int u = (k + 1) % 3, w = (k + 2) % 3;
         const int s = o2_sign64(A[u], A[w], B[u], B[w], C[u], C[w], st);
@@ -244,19 +284,26 @@ __device__ int drop_axis(const double* A, const double* B, const double* C, int&
     return -1;
 }
 
+template <int K>
+__device__ __forceinline__ bool in_tri_axis(const double* A, const double* B, const double* C, const double* P, int area,
+                                            QStats& st) {
+    constexpr int u = (K + 1) % 3, w = (K + 2) % 3;
+    if (o2_sign64(A[u], A[w], B[u], B[w], P[u], P[w], st) * area < 0) return false;
+    if (o2_sign64(B[u], B[w], C[u], C[w], P[u], P[w], st) * area < 0) return false;
+    if (o2_sign64(C[u], C[w], A[u], A[w], P[u], P[w], st) * area < 0) return false;
+    return true;
+}
+
 __device__ bool in_closed_tri_coplanar(const double* A, const double* B, const double* C, const double* P,
                                        QStats& st) {
     int area;
     const int k = drop_axis(A, B, C, area, st);
-    if (k < 0) return false;
-    const int u = (k + 1) % 3, w = (k + 2) % 3;
-    const double* V[3] = {A, B, C};
-    for (int i = 0; i < 3; i++) {
-        const double* p = V[i];
-        const double* q = V[(i + 1) % 3];
-        if (o2_sign64(p[u], p[w], q[u], q[w], P[u], P[w], st) * area < 0) return false;
+    switch (k) {  // compile-time axes keep the arrays in registers
+        case 0: return in_tri_axis<0>(A, B, C, P, area, st);
+        case 1: return in_tri_axis<1>(A, B, C, P, area, st);
+        case 2: return in_tri_axis<2>(A, B, C, P, area, st);
+        default: return false;
     }
-    return true;
 }
 
 // float64 value of orient3d (for hit parameters)
@@ -268,30 +315,42 @@ __device__ __forceinline__ double o3_value(const double* a, const double* b, con
 }
 
 // segment X->Y in the plane of T: entry parameter into the closed triangle
-__device__ int coplanar_clip(const double* A, const double* B, const double* C, const double* X, const double* Y,
-                             double& t, QStats& st) {
-    int area;
-    const int k = drop_axis(A, B, C, area, st);
-    if (k < 0) return 0;
-    const int u = (k + 1) % 3, w = (k + 2) % 3;
+template <int K>
+__device__ __forceinline__ int clip_axis(const double* A, const double* B, const double* C, const double* X,
+                                         const double* Y, int area, double& t, QStats& st) {
+    constexpr int u = (K + 1) % 3, w = (K + 2) % 3;
     const double* V[3] = {A, B, C};
     double lo = 0.0, hi = 1.0;
+    bool ok = true;
+#pragma unroll
     for (int i = 0; i < 3; i++) {
         const double* p = V[i];
         const double* q = V[(i + 1) % 3];
         const int g0 = o2_sign64(p[u], p[w], q[u], q[w], X[u], X[w], st) * area;
         const int g1 = o2_sign64(p[u], p[w], q[u], q[w], Y[u], Y[w], st) * area;
-        if (g0 < 0 && g1 < 0) return 0;
-        if (g0 >= 0 && g1 >= 0) continue;
+        if (g0 < 0 && g1 < 0) ok = false;
+        if (!ok || (g0 >= 0 && g1 >= 0)) continue;
         const double f0 = area * ((p[u] - X[u]) * (q[w] - X[w]) - (p[w] - X[w]) * (q[u] - X[u]));
         const double f1 = area * ((p[u] - Y[u]) * (q[w] - Y[w]) - (p[w] - Y[w]) * (q[u] - Y[u]));
         const double tt = f0 / (f0 - f1);
         if (g0 < 0) lo = fmax(lo, tt);
         else hi = fmin(hi, tt);
     }
-    if (lo > hi) return 0;
+    if (!ok || lo > hi) return 0;
     t = lo;
     return 1;
+}
+
+__device__ int coplanar_clip(const double* A, const double* B, const double* C, const double* X, const double* Y,
+                             double& t, QStats& st) {
+    int area;
+    const int k = drop_axis(A, B, C, area, st);
+    switch (k) {
+        case 0: return clip_axis<0>(A, B, C, X, Y, area, t, st);
+        case 1: return clip_axis<1>(A, B, C, X, Y, area, t, st);
+        case 2: return clip_axis<2>(A, B, C, X, Y, area, t, st);
+        default: return 0;
+    }
 }
 
 // Exact closed segment / closed triangle test in scaled global coordinates.
@@ -343,116 +402,292 @@ __device__ __forceinline__ int fast_test(const Cand<R>& C, const R X[3], const R
     return 1;
 }
 
+constexpr int CL_MAXC = 8;  // box-passing candidates kept per link and pass
+
+// packed nearest-hit key: t in [0,1] as 37-bit fixed point, then the
+// triangle id (27 bits); the minimum key is the nearest hit, ties (equal t to
+// 2^-37) going to the smallest triangle id
+constexpr double Q37 = 137438953471.0;  // 2^37 - 1
+constexpr unsigned long long KEY_MISS = ~0ull;
+__device__ __forceinline__ unsigned long long hit_key(double t, int tri) {
+    const double c = fmin(fmax(t, 0.0), 1.0);
+    return ((unsigned long long)(c * Q37 + 0.5) << 27) | (unsigned long long)(unsigned)tri;
+}
+
+// tasks per block: ceil(links / 64) x ceil(candidates / 64)
+__global__ void k_cl_ntask(int64_t nb, const int32_t* blk_off, const int32_t* loff, int64_t lcap, int32_t* ntask) {
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+        const int n = blk_off[b + 1] - blk_off[b];
+        int64_t c0 = loff[b], c1 = loff[b + 1];
+        if (c1 > lcap) c1 = lcap;
+        const int nc = c1 > c0 ? (int)(c1 - c0) : 0;
+        ntask[b] = n > 0 ? ((n + 63) / 64) * (nc > 0 ? (nc + CL_CAND - 1) / CL_CAND : 1) : 0;
+    }
+}
+
+__global__ void k_cl_fill_keys(unsigned long long* keys, int32_t* mark, const int64_t* d_n, int64_t cap) {
+    int64_t n = *d_n;
+    if (n > cap) n = cap;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        keys[i] = KEY_MISS;
+        mark[i] = 0;
+    }
+}
+
+__global__ void k_cl_final(const unsigned long long* keys, const int64_t* d_n, int64_t cap, float* link_q,
+                           int32_t* link_tri) {
+    int64_t n = *d_n;
+    if (n > cap) n = cap;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long k = keys[i];
+        if (k == KEY_MISS) {
+            link_q[i] = -1.0f;
+            link_tri[i] = -1;
+        } else {
+            link_q[i] = (float)((double)(k >> 27) / Q37);
+            link_tri[i] = (int32_t)(k & ((1ull << 27) - 1));
+        }
+    }
+}
+
+// block of a task: largest b with task_off[b] <= task (64-ary search by the wave)
+__device__ __forceinline__ int64_t task_block(const int32_t* task_off, int64_t nb, int task) {
+    int64_t lo = 0, hi = nb;  // task_off[lo] <= task < task_off[hi]
+    const int lane = threadIdx.x;
+    while (hi - lo > 1) {
+        const int64_t span = hi - lo;
+        const int64_t step = (span + 63) / 64;
+        const int64_t pos = lo + (int64_t)lane * step;
+        const bool le = pos < hi && task_off[pos] <= task;
+        const unsigned long long m = __ballot(le);
+        const int last = 63 - __clzll((long long)m);  // lane 0 always qualifies
+        const int64_t nlo = lo + (int64_t)last * step;
+        const int64_t nhi = (nlo + step < hi) ? nlo + step : hi;
+        lo = nlo;
+        hi = nhi;
+    }
+    return lo;
+}
+
 template <typename R>
-__global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_t* loff, const int32_t* lval,
-                                             int64_t lcap, const uint32_t* link_mask, const int32_t* blk_off,
-                                             int64_t cap, int32_t* link_cell, uint8_t* link_dir, float* link_q,
-                                             int32_t* link_tri, uint64_t* stats) {
+__global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_t* roff, const int32_t* rval,
+                                             int64_t rcap, const int32_t* loff, const int32_t* lval, int64_t lcap,
+                                             int lattice, const int32_t* blk_off, const int32_t* task_off,
+                                             int64_t cap, int32_t* link_cell, uint8_t* link_dir,
+                                             unsigned long long* keys, int32_t* mark, int32_t* fixq,
+                                             int32_t* fixn, uint64_t* stats) {
     __shared__ Cand<R> cand[CL_CAND];
+    __shared__ CBox cbox[CL_CAND];
     __shared__ uint32_t smask[64];
     __shared__ int spre[65];
+    __shared__ unsigned halo[36];
+    __shared__ uint8_t plist[64 * CL_MAXC];   // per link: box-passing candidate slots
+    __shared__ int ppre[65];                  // prefix of the per-link counts
+    __shared__ unsigned long long pkey[64 * CL_MAXC];  // phase-2 results
+    __shared__ int sk[64];                    // link (t, k) of each lane, packed t | k << 8
     const int L = d.level;
-    const double s = ldexp(1.0, L);
     const int lane = threadIdx.x;
+    const uint32_t dirs = lattice_dirs(lattice);
+    const int ntasks = task_off[d.nblocks];
+    // contiguous task range per workgroup, so that consecutive tasks share a block
+    const int per = (ntasks + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int t0 = (int)blockIdx.x * per;
+    const int t1 = t0 + per < ntasks ? t0 + per : ntasks;
     QStats st;
-    for (int64_t b = blockIdx.x; b < d.nblocks; b += gridDim.x) {
+    if (t0 >= t1) return;
+    int64_t b = task_block(task_off, d.nblocks, t0);
+    int64_t b_prev = -1;
+    for (int task = t0; task < t1; task++) {
+        while (task >= task_off[b + 1]) b++;  // uniform
         const int n = blk_off[b + 1] - blk_off[b];
-        if (n == 0) continue;  // uniform across the workgroup
-        const int b0[3] = {4 * d.bcoord[3 * b], 4 * d.bcoord[3 * b + 1], 4 * d.bcoord[3 * b + 2]};
-        const uint32_t mk = link_mask[64 * b + lane];
-        smask[lane] = mk;
-        int c = __popc(mk), incl = c;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int tt = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += tt;
-        }
-        spre[lane] = incl - c;
-        if (lane == 63) spre[64] = incl;
         int64_t c0 = loff[b], c1 = loff[b + 1];
         if (c1 > lcap) c1 = lcap;
         if (c0 > c1) c0 = c1;
         const int nc = (int)(c1 - c0);
+        const int ncc = nc > 0 ? (nc + CL_CAND - 1) / CL_CAND : 1;
+        const int local = task - task_off[b];
+        const int lchunk = local / ncc, cchunk = local % ncc;
+        const int b0[3] = {4 * d.bcoord[3 * b], 4 * d.bcoord[3 * b + 1], 4 * d.bcoord[3 * b + 2]};
+        if (b != b_prev) {  // uniform
+            const uint32_t mk = block_link_mask(d, roff, rval, rcap, dirs, b, halo);
+            smask[lane] = mk;
+            int c = __popc(mk), incl = c;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int tt = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += tt;
+            }
+            spre[lane] = incl - c;
+            if (lane == 63) spre[64] = incl;
+            b_prev = b;
+        }
+        const int cb = cchunk * CL_CAND;
+        const int nstage = nc - cb < CL_CAND ? (nc - cb > 0 ? nc - cb : 0) : CL_CAND;
         __syncthreads();
-        for (int lbase = 0; lbase < n; lbase += 64) {
-            const int li = lbase + lane;
-            const bool active = li < n;
-            int t = 0, k = 0;
-            if (active) {
-                int lo = 0, hi = 63;  // largest t with spre[t] <= li
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (spre[mid] <= li) lo = mid;
-                    else hi = mid - 1;
-                }
-                t = lo;
-                int r = li - spre[t];
-                uint32_t mm = smask[t];
-                for (int q = 0; q < r; q++) mm &= mm - 1u;
-                k = __ffs(mm) - 1;
-            }
-            int cx, cy, cz;
-            dirvec(k, cx, cy, cz);
-            const int Xi[3] = {t & 3, (t >> 2) & 3, t >> 4};
-            const R X[3] = {(R)Xi[0], (R)Xi[1], (R)Xi[2]};
-            const R Y[3] = {(R)(Xi[0] + cx), (R)(Xi[1] + cy), (R)(Xi[2] + cz)};
-            double best = 2.0;
-            int btri = 0x7fffffff;
-            for (int cb = 0; cb < nc; cb += CL_CAND) {
-                const int nstage = nc - cb < CL_CAND ? nc - cb : CL_CAND;
-                __syncthreads();
-                if (lane < nstage) stage_cand<R>(m, L, lval[c0 + cb + lane], b0, cand[lane]);
-                __syncthreads();
-                if (!active) continue;
-                for (int ci = 0; ci < nstage; ci++) {
-                    const Cand<R>& C = cand[ci];
-                    if (C.flags & C_SKIP) continue;
-                    double tq;
-                    int res;
-                    R tr = 0, terr = 0;
-                    res = (C.flags & C_SLOW) ? -1 : fast_test<R>(C, X, Y, tr, terr);
-                    if (res < 0) {
-                        if constexpr (std::is_same<R, float>::value) st.fb++;
-                        double A[3], B[3], Cc[3];
-                        vert_scaled(m, m.tris[3 * (int64_t)C.tri], s, A);
-                        vert_scaled(m, m.tris[3 * (int64_t)C.tri + 1], s, B);
-                        vert_scaled(m, m.tris[3 * (int64_t)C.tri + 2], s, Cc);
-                        const double Xg[3] = {(double)(b0[0] + Xi[0]), (double)(b0[1] + Xi[1]), (double)(b0[2] + Xi[2])};
-                        const double Yg[3] = {Xg[0] + cx, Xg[1] + cy, Xg[2] + cz};
-                        res = exact_seg_hit(A, B, Cc, Xg, Yg, tq, st);
-                    } else if (res == 1) {
-                        tq = (double)tr;
-                        if (terr > (R)2e-6) {
-                            // ill-conditioned: refine t with the float64 plane
-                            st.tq++;
-                            const double sX = C.off64 - C.n64[0] * Xi[0] - C.n64[1] * Xi[1] - C.n64[2] * Xi[2];
-                            const double nd = C.n64[0] * cx + C.n64[1] * cy + C.n64[2] * cz;
-                            tq = sX / nd;
-                            tq = fmin(fmax(tq, 0.0), 1.0);
-                        }
-                    }
-                    if (res == 1 && (tq < best || (tq == best && C.tri < btri))) {
-                        best = tq;
-                        btri = C.tri;
-                    }
-                }
-            }
-            if (active) {
-                const int64_t pos = (int64_t)blk_off[b] + li;
-                if (pos < cap) {
-                    link_cell[pos] = (int32_t)(64 * b + t);
-                    link_dir[pos] = (uint8_t)k;
-                    link_q[pos] = best <= 1.0 ? (float)best : -1.0f;
-                    link_tri[pos] = best <= 1.0 ? btri : -1;
-                }
-            }
+        if (lane < nstage) {
+            stage_cand<R>(m, L, lval[c0 + cb + lane], b0, cand[lane], cbox[lane]);
+            st.staged++;
         }
         __syncthreads();
+        const int li = lchunk * 64 + lane;
+        const bool active = li < n;
+        int t = 0, k = 13;
+        if (active) {
+            int lo = 0, hi = 63;  // largest t with spre[t] <= li
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (spre[mid] <= li) lo = mid;
+                else hi = mid - 1;
+            }
+            t = lo;
+            int r = li - spre[t];
+            uint32_t mm = smask[t];
+            for (int q = 0; q < r; q++) mm &= mm - 1u;
+            k = __ffs(mm) - 1;
+        }
+        sk[lane] = t | (k << 8);
+        int cx, cy, cz;
+        dirvec(k, cx, cy, cz);
+        const float slo[3] = {(float)geo_min(t & 3, (t & 3) + cx), (float)geo_min((t >> 2) & 3, ((t >> 2) & 3) + cy),
+                              (float)geo_min(t >> 4, (t >> 4) + cz)};
+        const float shi[3] = {(float)geo_max(t & 3, (t & 3) + cx), (float)geo_max((t >> 2) & 3, ((t >> 2) & 3) + cy),
+                              (float)geo_max(t >> 4, (t >> 4) + cz)};
+        const int64_t lbase = (int64_t)blk_off[b] + lchunk * 64;
+        unsigned long long best = KEY_MISS;
+        int ci = 0;
+        while (ci < nstage) {  // uniform
+            // phase 1: box tests, each lane lists its passing candidates
+            int cnt = 0;
+            for (; ci < nstage; ci++) {
+                const float4 lo4 = cbox[ci].lo, hi4 = cbox[ci].hi;
+                const bool pass = active && !(hi4.x < slo[0] || lo4.x > shi[0] || hi4.y < slo[1] ||
+                                              lo4.y > shi[1] || hi4.z < slo[2] || lo4.z > shi[2]);
+                if (pass) plist[lane * CL_MAXC + cnt++] = (uint8_t)ci;
+                if (__any(cnt == CL_MAXC)) { ci++; break; }
+            }
+            // flatten the (link, candidate) pairs over the wave
+            int inc2 = cnt;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int tt = __shfl_up(inc2, o, 64);
+                if (lane >= o) inc2 += tt;
+            }
+            ppre[lane] = inc2 - cnt;
+            if (lane == 63) ppre[64] = inc2;
+            __syncthreads();
+            const int P = ppre[64];
+            st.pairs += cnt;
+            // phase 2: one pair per lane
+            for (int p = lane; p < P; p += 64) {
+                int lo = 0, hi = 63;  // owner: largest l with ppre[l] <= p
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (ppre[mid] <= p) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int ow = lo;
+                const int cidx = plist[ow * CL_MAXC + (p - ppre[ow])];
+                const int tk = sk[ow];
+                const int ot = tk & 0xff, ok = tk >> 8;
+                int ox, oy, oz;
+                dirvec(ok, ox, oy, oz);
+                const int Xi[3] = {ot & 3, (ot >> 2) & 3, ot >> 4};
+                const R X[3] = {(R)Xi[0], (R)Xi[1], (R)Xi[2]};
+                const R Y[3] = {(R)(Xi[0] + ox), (R)(Xi[1] + oy), (R)(Xi[2] + oz)};
+                const Cand<R>& C = cand[cidx];
+                const int flags = (int)cbox[cidx].lo.w;
+                R tr = 0, terr = 0;
+                const int res = (flags & C_SLOW) ? -1 : fast_test<R>(C, X, Y, tr, terr);
+                unsigned long long kk = KEY_MISS;
+                if (res == 1) {
+                    // hit parameter from the float64 plane
+                    const double sX = C.off64 - C.n64[0] * Xi[0] - C.n64[1] * Xi[1] - C.n64[2] * Xi[2];
+                    const double nd = C.n64[0] * ox + C.n64[1] * oy + C.n64[2] * oz;
+                    kk = hit_key(sX / nd, C.tri);
+                } else if (res < 0) {
+                    // not certain: the link is redone exactly by the deferred pass
+                    st.fb++;
+                    const int64_t pos = lbase + ow;
+                    if (pos < cap && atomicExch(&mark[pos], 1) == 0) {
+                        const int qi = atomicAdd(fixn, 1);
+                        if (qi < cap) fixq[qi] = (int32_t)pos;
+                    }
+                }
+                pkey[p] = kk;
+            }
+            __syncthreads();
+            // phase 3: each link keeps its nearest hit
+            for (int j = 0; j < cnt; j++) {
+                const unsigned long long kk = pkey[ppre[lane] + j];
+                best = kk < best ? kk : best;
+            }
+            __syncthreads();
+        }
+        if (active) {
+            const int64_t pos = lbase + lane;
+            if (pos < cap) {
+                if (cchunk == 0) {
+                    link_cell[pos] = (int32_t)(64 * b + t);
+                    link_dir[pos] = (uint8_t)k;
+                }
+                if (best != KEY_MISS) atomicMin(&keys[pos], best);
+            }
+        }
     }
     if (stats) {
-        if constexpr (std::is_same<R, float>::value) wave_count(&stats[GEO_STAT_F32_TO_F64], st.fb);
+        wave_count(&stats[GEO_STAT_F32_TO_F64], st.fb);
+        wave_count(&stats[GEO_STAT_STAGED], st.staged);
+        wave_count(&stats[GEO_STAT_PAIRS], st.pairs);
+    }
+}
+
+// Deferred exact pass: each queued link is tested against all candidates of
+// its block with exact predicates (one wave per link, lanes split the
+// candidates); the result is folded into its key.
+__global__ void __launch_bounds__(64) k_cl_fix(DevMesh m, DevLevel d, const int32_t* loff, const int32_t* lval,
+                                               int64_t lcap, const int32_t* link_cell, const uint8_t* link_dir,
+                                               const int32_t* fixq, const int32_t* fixn, int64_t cap,
+                                               unsigned long long* keys, uint64_t* stats) {
+    int64_t nq = *fixn;
+    if (nq > cap) nq = cap;
+    const double s = ldexp(1.0, d.level);
+    QStats st;
+    for (int64_t i = blockIdx.x; i < nq; i += gridDim.x) {
+        const int64_t pos = fixq[i];
+        const int cell = link_cell[pos];
+        const int64_t b = cell >> 6;
+        const int t = cell & 63;
+        int cx, cy, cz;
+        dirvec(link_dir[pos], cx, cy, cz);
+        const double X[3] = {(double)(4 * d.bcoord[3 * b] + (t & 3)), (double)(4 * d.bcoord[3 * b + 1] + ((t >> 2) & 3)),
+                             (double)(4 * d.bcoord[3 * b + 2] + (t >> 4))};
+        const double Y[3] = {X[0] + cx, X[1] + cy, X[2] + cz};
+        int64_t c0 = loff[b], c1 = loff[b + 1];
+        if (c1 > lcap) c1 = lcap;
+        unsigned long long best = KEY_MISS;
+        for (int64_t c = c0 + threadIdx.x; c < c1; c += 64) {
+            const int tri = lval[c];
+            double A[3], B[3], Cc[3];
+            vert_scaled(m, m.tris[3 * (int64_t)tri], s, A);
+            vert_scaled(m, m.tris[3 * (int64_t)tri + 1], s, B);
+            vert_scaled(m, m.tris[3 * (int64_t)tri + 2], s, Cc);
+            double tq;
+            if (exact_seg_hit(A, B, Cc, X, Y, tq, st)) {
+                const unsigned long long kk = hit_key(tq, tri);
+                best = kk < best ? kk : best;
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long other = __shfl_xor(best, o, 64);
+            best = other < best ? other : best;
+        }
+        if (threadIdx.x == 0 && best != KEY_MISS) atomicMin(&keys[pos], best);
+        if (threadIdx.x == 0) st.tq++;
+    }
+    if (stats) {
         wave_count(&stats[GEO_STAT_EXACT], st.ex);
-        wave_count(&stats[GEO_STAT_Q_F64], st.tq);
+        wave_count(&stats[GEO_STAT_LINKS_EXACT], st.tq);
     }
 }
 
@@ -460,8 +695,11 @@ inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
-size_t geo_cutlinks_ws_bytes(int64_t nb) {
-    return al(sizeof(int32_t) * (size_t)nb) + al(sizeof(int32_t) * ((size_t)nb + 1)) + al(geo_scan_partials_bytes(nb));
+size_t geo_cutlinks_ws_bytes(int64_t nb, int64_t cap) {
+    const size_t c = (size_t)(cap > 0 ? cap : 1);
+    return 2 * al(sizeof(int32_t) * (size_t)nb) + 2 * al(sizeof(int32_t) * ((size_t)nb + 1)) +
+           al(geo_scan_partials_bytes(nb)) + al(sizeof(unsigned long long) * c) + 2 * al(sizeof(int32_t) * c) +
+           al(sizeof(int32_t));
 }
 
 int launch_cutlinks(const DevMesh& m, const DevLevel& d, const geo_bins* rows, const geo_bins* links, int lattice,
@@ -469,13 +707,26 @@ int launch_cutlinks(const DevMesh& m, const DevLevel& d, const geo_bins* rows, c
                     uint8_t* link_dir, float* link_q, int32_t* link_tri, uint64_t* d_stats, void* ws,
                     size_t ws_bytes, hipStream_t s) {
     const int64_t nb = d.nblocks;
-    if (ws_bytes < geo_cutlinks_ws_bytes(nb)) return GEO_ERR_WORKSPACE;
+    if (ws_bytes < geo_cutlinks_ws_bytes(nb, cap)) return GEO_ERR_WORKSPACE;
+    const size_t c = (size_t)(cap > 0 ? cap : 1);
     char* p = static_cast<char*>(ws);
     int32_t* blk_cnt = reinterpret_cast<int32_t*>(p);
     p += al(sizeof(int32_t) * (size_t)nb);
     int32_t* blk_off = reinterpret_cast<int32_t*>(p);
     p += al(sizeof(int32_t) * ((size_t)nb + 1));
+    int32_t* ntask = reinterpret_cast<int32_t*>(p);
+    p += al(sizeof(int32_t) * (size_t)nb);
+    int32_t* task_off = reinterpret_cast<int32_t*>(p);
+    p += al(sizeof(int32_t) * ((size_t)nb + 1));
     int32_t* partials = reinterpret_cast<int32_t*>(p);
+    p += al(geo_scan_partials_bytes(nb));
+    unsigned long long* keys = reinterpret_cast<unsigned long long*>(p);
+    p += al(sizeof(unsigned long long) * c);
+    int32_t* mark = reinterpret_cast<int32_t*>(p);
+    p += al(sizeof(int32_t) * c);
+    int32_t* fixq = reinterpret_cast<int32_t*>(p);
+    p += al(sizeof(int32_t) * c);
+    int32_t* fixn = reinterpret_cast<int32_t*>(p);
     if (nb == 0) return geo_fill_u64(reinterpret_cast<uint64_t*>(d_nlinks), 0, 1, s);
     const unsigned g = (unsigned)(nb < 262144 ? nb : 262144);
     k_cl_mask<<<g, 64, 0, s>>>(d, rows->off, rows->val, rows->cap, lattice, link_mask, blk_cnt);
@@ -483,12 +734,30 @@ int launch_cutlinks(const DevMesh& m, const DevLevel& d, const geo_bins* rows, c
     int rc = geo_scan_exclusive(blk_cnt, blk_off, nb, partials, s);
     if (rc != GEO_OK) return rc;
     k_cl_total<<<1, 64, 0, s>>>(blk_off, nb, d_nlinks);
-    if (precision == GEO_PREC_F32_FALLBACK)
-        k_cl_q<float><<<g, 64, 0, s>>>(m, d, links->off, links->val, links->cap, link_mask, blk_off, cap, link_cell,
-                                       link_dir, link_q, link_tri, d_stats);
-    else
-        k_cl_q<double><<<g, 64, 0, s>>>(m, d, links->off, links->val, links->cap, link_mask, blk_off, cap,
-                                        link_cell, link_dir, link_q, link_tri, d_stats);
+    const unsigned gb = (unsigned)((nb + 255) / 256 < 65536 ? (nb + 255) / 256 : 65536);
+    k_cl_ntask<<<gb, 256, 0, s>>>(nb, blk_off, links->off, links->cap, ntask);
     GEO_LAUNCH_CHECK();
+    if ((rc = geo_scan_exclusive(ntask, task_off, nb, partials, s)) != GEO_OK) return rc;
+    if (cap > 0) {
+        k_cl_fill_keys<<<8192, 256, 0, s>>>(keys, mark, d_nlinks, cap);
+        if ((rc = geo_fill_i32(fixn, 0, 1, s)) != GEO_OK) return rc;
+        GEO_LAUNCH_CHECK();
+    }
+    const unsigned gq = 16384;
+    if (precision == GEO_PREC_F32_FALLBACK)
+        k_cl_q<float><<<gq, 64, 0, s>>>(m, d, rows->off, rows->val, rows->cap, links->off, links->val, links->cap,
+                                        lattice, blk_off, task_off, cap, link_cell, link_dir, keys, mark, fixq, fixn,
+                                        d_stats);
+    else
+        k_cl_q<double><<<gq, 64, 0, s>>>(m, d, rows->off, rows->val, rows->cap, links->off, links->val, links->cap,
+                                         lattice, blk_off, task_off, cap, link_cell, link_dir, keys, mark, fixq, fixn,
+                                         d_stats);
+    GEO_LAUNCH_CHECK();
+    if (cap > 0) {
+        k_cl_fix<<<4096, 64, 0, s>>>(m, d, links->off, links->val, links->cap, link_cell, link_dir, fixq, fixn, cap,
+                                     keys, d_stats);
+        k_cl_final<<<8192, 256, 0, s>>>(keys, d_nlinks, cap, link_q, link_tri);
+        GEO_LAUNCH_CHECK();
+    }
     return GEO_OK;
 }

@@ -13,6 +13,12 @@ GEO_HD __forceinline__ double geo_fabs(double x) { return x < 0 ? -x : x; }
 GEO_HD __forceinline__ float geo_fabs(float x) { return x < 0 ? -x : x; }
 template <typename R> GEO_HD __forceinline__ R geo_max(R a, R b) { return a > b ? a : b; }
 template <typename R> GEO_HD __forceinline__ R geo_min(R a, R b) { return a < b ? a : b; }
+// element k of (a0, a1, a2) as a value select, so that arrays stay in registers
+// (a select over loads from one array would be folded into a dynamic index)
+template <typename R> GEO_HD __forceinline__ R pick3(R a0, R a1, R a2, int k) {
+    return k == 0 ? a0 : (k == 1 ? a1 : a2);
+}
+#define SEL3(a, k) pick3((a)[0], (a)[1], (a)[2], (k))
 
 // --------------------------------------------------------------------------
 // kernel-side copies of the level / mesh descriptors (passed by value)

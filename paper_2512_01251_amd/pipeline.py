@@ -35,7 +35,7 @@ class Level:
 
 @dataclass
 class Links:
-    mask: torch.Tensor                   # int32 [nb*64] (uint32 bits)
+    mask: torch.Tensor                   # int32 [nb*64] (uint32 bits), or None
     cell: torch.Tensor                   # int32 [n]
     dir: torch.Tensor                    # uint8 [n]
     q: torch.Tensor                      # float32 [n]
@@ -80,7 +80,8 @@ class Embedder:
 
     # -- the path ----------------------------------------------------------------
     def embed(self, verts: torch.Tensor, tris: torch.Tensor, n0, lf: int, lattice: int,
-              d_spec: float = 2.0, precision: str = "f32", with_links: bool = True) -> Embedding:
+              d_spec: float = 2.0, precision: str = "f32", with_links: bool = True,
+              with_mask: bool = False) -> Embedding:
         dev = self.device
         prec = PRECISIONS[precision]
         mesh = make_mesh(verts, tris)
@@ -120,7 +121,7 @@ class Embedder:
                 self._rows_last = rows
             out.levels.append(rec)
         if with_links:
-            out.links = self._cutlinks(mesh, n0, lf, out.levels[-1], child_maps, lattice, prec, stats)
+            out.links = self._cutlinks(mesh, n0, lf, out.levels[-1], child_maps, lattice, prec, stats, with_mask)
         out.stats = stats
         return out
 
@@ -143,7 +144,7 @@ class Embedder:
             cap = int(need * 1.1) + 1024
         raise RuntimeError("bins capacity did not converge")
 
-    def _cutlinks(self, mesh, n0, lf, rec, child_maps, lattice, prec, stats):
+    def _cutlinks(self, mesh, n0, lf, rec, child_maps, lattice, prec, stats, with_mask):
         dev = self.device
         lvd = make_level(n0, lf, rec.bcoord, child_maps)
         nb = lvd.nblocks
@@ -152,11 +153,11 @@ class Embedder:
         links = make_bins(GEO_BINS_LINKS, nb, loff, lval, lval.numel(), self._count)
         rows = make_bins(GEO_BINS_ROWS, (n0[1] << lf) * (n0[2] << lf), rec.rows_off, rec.rows_val,
                          rec.rows_val.numel(), self._count)
-        mask = torch.empty(nb * 64, dtype=torch.int32, device=dev)
+        mask = torch.empty(nb * 64, dtype=torch.int32, device=dev) if with_mask else None
         d_n = torch.zeros(1, dtype=torch.int64, device=dev)
         cap = self.caps.get(("links_table", lf), max(4096, 4 * nb))
-        ws = self._workspace(geo_workspace_size(GEO_CALL_CUTLINKS, nb, 0))
         for _ in range(3):
+            ws = self._workspace(geo_workspace_size(GEO_CALL_CUTLINKS, nb, cap))
             cell = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
             dr = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
             q = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
@@ -195,8 +196,9 @@ class _Timer:
         return False
 
 
-def embed(verts, tris, n0, lf, lattice, d_spec=2.0, precision="f32", with_links=True) -> Embedding:
-    return Embedder(verts.device).embed(verts, tris, n0, lf, lattice, d_spec, precision, with_links)
+def embed(verts, tris, n0, lf, lattice, d_spec=2.0, precision="f32", with_links=True,
+          with_mask=False) -> Embedding:
+    return Embedder(verts.device).embed(verts, tris, n0, lf, lattice, d_spec, precision, with_links, with_mask)
 
 
 # ----------------------------------------------------------------------------

@@ -114,6 +114,23 @@ def _real_sh(l: int, m: int, theta: np.ndarray, phi: np.ndarray) -> np.ndarray:
     return math.sqrt(2.0) * norm * p * np.sin(am * phi)
 
 
+def _legendre_factor(l: int, m: int, theta: np.ndarray) -> np.ndarray:
+    """theta factor N_l|m| P_l^|m|(cos theta) of the real harmonic."""
+    am = abs(m)
+    norm = math.sqrt((2 * l + 1) / (4 * math.pi)
+                     * math.factorial(l - am) / math.factorial(l + am))
+    return norm * lpmv(am, l, np.cos(theta))
+
+
+def _trig(m: int, phi: np.ndarray) -> np.ndarray:
+    """phi factor of the real harmonic, with the sqrt(2) of m != 0 folded in."""
+    if m == 0:
+        return np.ones_like(phi)
+    if m > 0:
+        return math.sqrt(2.0) * np.cos(m * phi)
+    return math.sqrt(2.0) * np.sin(-m * phi)
+
+
 def sh_coefficients(seed: int, lmax: int = 8) -> list:
     """a_lm ~ N(0, 1/l^2), drawn with NumPy PCG64 in order l = 1..lmax, m = -l..l."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -146,9 +163,14 @@ def latlong_star(n_theta: int, n_phi: int, radius: float, centre, seed: int,
     used_seed = seed
     for _ in range(max_redraws):
         coeffs = sh_coefficients(used_seed, lmax)
-        s = np.zeros_like(th)
+        # the sum is separable on the lat-long grid: Legendre factors per ring
+        # times trigonometric factors per sector (poles evaluated directly)
+        ring = np.zeros((n_theta - 1, n_phi))
+        poles = np.zeros(2)
         for (l, m, a) in coeffs:
-            s += a * _real_sh(l, m, th, ph)
+            ring += a * np.outer(_legendre_factor(l, m, theta_r), _trig(m, phi_r))
+            poles += a * _real_sh(l, m, np.array([0.0, math.pi]), np.zeros(2))
+        s = np.concatenate([[poles[0]], ring.ravel(), [poles[1]]])
         r = radius * (1.0 + amplitude * s)
         V = np.stack([r * np.sin(th) * np.cos(ph),
                       r * np.sin(th) * np.sin(ph),

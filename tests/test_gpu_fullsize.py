@@ -1,0 +1,140 @@
+"""GPU parity at the full benchmark sizes.
+
+star112k (112,000 triangles, 128^3 base, levels 0..3, D3Q19): the whole
+forest is compared with the oracle (every cell of every level, classes,
+marks, child maps); links on a random sample.
+
+star7m (7,200,000 triangles, float32 vertices, 256^3 base, levels 0..4,
+D3Q27; the benchmark workload in the benchmark's launch configuration):
+sampled cells and links against the oracle's point functions, and
+invariants that hold at any size.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import configs
+from gpu_helpers import gpu_embed, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _cells_of(bcoord, blocks, t):
+    return 4 * bcoord[blocks] + np.stack([t & 3, (t >> 2) & 3, t >> 4], 1)
+
+
+def _check_links_sample(w, emb, rng, n):
+    lv = emb.levels[-1]
+    L = lv.level
+    bc = lv.bcoord.cpu().numpy()
+    Lk = emb.links
+    idx = rng.choice(Lk.n, min(n, Lk.n), replace=False)
+    cell = Lk.cell.cpu().numpy()[idx]
+    dirs = Lk.dir.cpu().numpy()[idx]
+    cells = _cells_of(bc, cell // 64, cell % 64)
+    ref = oracle.q_points(w.mesh, w.n0, L, cells, dirs)
+    q = Lk.q.cpu().numpy()[idx].astype(np.float64)
+    err = np.abs(q - ref["q"])
+    assert err.max() <= 1e-5, err.max()
+    tri = Lk.tri.cpu().numpy()[idx]
+    untied = ref["tied"] == 0
+    assert np.array_equal(tri[untied], ref["tri"][untied])
+    # the link joins a fluid centre to a solid one
+    c = np.array([[k % 3 - 1, (k // 3) % 3 - 1, k // 9 - 1] for k in range(27)])
+    X = (cells + 0.5) * 2.0 ** -L
+    Y = (cells + c[dirs] + 0.5) * 2.0 ** -L
+    assert not oracle.solid_points(w.mesh, w.n0, X).any()
+    assert oracle.solid_points(w.mesh, w.n0, Y).all()
+    return float(err.max())
+
+
+def _check_cells_sample(w, emb, rng, n):
+    for lv in emb.levels:
+        bc = lv.bcoord.cpu().numpy()
+        solid = lv.solid.cpu().numpy().view(np.uint64)
+        mixed = np.nonzero((solid != 0) & (solid != np.uint64(0xFFFFFFFFFFFFFFFF)))[0]
+        b = np.concatenate([rng.integers(0, len(bc), n // 2),
+                            mixed[rng.integers(0, len(mixed), n // 2)] if len(mixed) else []]).astype(np.int64)
+        t = rng.integers(0, 64, len(b))
+        cells = _cells_of(bc, b, t)
+        ref = oracle.solid_points(w.mesh, w.n0, (cells + 0.5) * 2.0 ** -lv.level)
+        got = ((solid[b] >> t.astype(np.uint64)) & np.uint64(1)).astype(np.uint8)
+        assert np.array_equal(got, ref), f"level {lv.level}: {np.count_nonzero(got != ref)} of {len(b)}"
+
+
+def _check_invariants(w, emb):
+    lv = emb.levels
+    for L in range(1, len(lv)):
+        par = lv[L - 1].bcoord.cpu().numpy().astype(np.int64)
+        dims = np.array(w.n0) // 4 * 2 ** (L - 1)
+        key = lambda c: (c[:, 2] * dims[1] + c[:, 1]) * dims[0] + c[:, 0]
+        pk = np.sort(key(par))
+        ch = lv[L].bcoord.cpu().numpy().astype(np.int64)
+        parents = np.unique(ch // 2, axis=0)
+        # children come in complete octets, in parent order
+        ref = lv[L - 1].refine.cpu().numpy().astype(bool)
+        assert len(ch) == 8 * ref.sum()
+        assert np.array_equal(ch[::8] // 2, par[ref])
+        # 2:1 balance: every in-domain 26-neighbour of a refined parent exists
+        for d in np.array(np.meshgrid([-1, 0, 1], [-1, 0, 1], [-1, 0, 1])).reshape(3, -1).T:
+            q = parents + d
+            ok = ((q >= 0) & (q < dims)).all(1)
+            found = np.isin(key(q[ok]), pk)
+            assert found.all(), f"level {L}: refined parent with a missing neighbour"
+    # coverage: every vertex lies in a finest-level block
+    L = len(lv) - 1
+    dims = np.array(w.n0) // 4 * 2 ** L
+    fb = lv[-1].bcoord.cpu().numpy().astype(np.int64)
+    fk = np.sort((fb[:, 2] * dims[1] + fb[:, 1]) * dims[0] + fb[:, 0])
+    vb = np.floor(w.mesh.verts.astype(np.float64) * 2 ** L / 4).astype(np.int64)
+    vk = (vb[:, 2] * dims[1] + vb[:, 1]) * dims[0] + vb[:, 0]
+    assert np.isin(vk, fk).all()
+    # link table order (block, t, k)
+    cell = emb.links.cell.cpu().numpy().astype(np.int64)
+    dr = emb.links.dir.cpu().numpy().astype(np.int64)
+    key = cell * 32 + dr
+    assert (np.diff(key) > 0).all()
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = configs.star112k()
+    say("[fullsize] star112k oracle forest ...")
+    ref = oracle.embed(w.mesh, w.n0, w.lf, w.lattice, w.d_spec, with_links=False)
+    return w, ref
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_star112k_forest_exact_and_links_sampled(c1, precision):
+    w, ref = c1
+    say(f"[fullsize] star112k {precision}")
+    emb, _, _ = gpu_embed(w, precision)
+    for g, r in zip(emb.levels, ref["levels"]):
+        assert np.array_equal(g.bcoord.cpu().numpy(), r["bcoord"])
+        assert np.array_equal(g.solid.cpu().numpy().view(np.uint64), r["solid"]), f"solid L{r['level']}"
+        if "refine" in r:
+            assert np.array_equal(g.bclass.cpu().numpy(), r["bclass"])
+            assert np.array_equal(g.refine.cpu().numpy(), r["refine"])
+            assert np.array_equal(g.child_map.cpu().numpy(), r["child_map"])
+    _check_invariants(w, emb)
+    e = _check_links_sample(w, emb, np.random.default_rng(1), 20000)
+    say(f"[fullsize] star112k {precision} ok: {emb.links.n} links, sampled max |dq| {e:.2e}")
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return configs.star7m()
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_star7m_sampled(c2, precision):
+    w = c2
+    say(f"[fullsize] star7m {precision}")
+    emb, _, _ = gpu_embed(w, precision)
+    rng = np.random.default_rng(2)
+    _check_invariants(w, emb)
+    _check_cells_sample(w, emb, rng, 4000)
+    e = _check_links_sample(w, emb, rng, 3000)
+    st = emb.stats.cpu().numpy()
+    say(f"[fullsize] star7m {precision} ok: {emb.links.n} links, sampled max |dq| {e:.2e}, stats {st.tolist()}")
+    assert st[3] == 0
