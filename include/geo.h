@@ -140,7 +140,8 @@ int geo_level0_blocks(const int32_t n0[3], int32_t* bcoord, geo_stream_t stream)
  *   The entry order within a line is unspecified.  The arithmetic form is
  *   selected by precision; both give identical entries.
  * LINKS: for every block of the level, the ids of the triangles that overlap
- *   the block's box widened by h on every side (conservative).
+ *   the block's box widened by h/2 on every side, the region reached by the
+ *   links of its cells (conservative; zero-area triangles are left out).
  *
  * mesh, lv: inputs (device arrays).  out: CSR with out->nkeys as above.
  * d_stats: device uint64[GEO_NSTATS], accumulated (may be NULL).

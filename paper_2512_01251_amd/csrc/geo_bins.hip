@@ -461,9 +461,9 @@ __global__ void __launch_bounds__(64) k_links_pass1(DevMesh m, DevLevel d, int32
             const int nb[3] = {nbx, nby, nbz};
             for (int a = 0; a < 3; a++) {
                 const double mn = fmin(v[0][a], fmin(v[1][a], v[2][a])), mx = fmax(v[0][a], fmax(v[1][a], v[2][a]));
-                // block b's widened box is [4bh - h, 4bh + 5h]
-                lo[a] = (int)ceil((mn - 5.0 * h) / bw);
-                hi[a] = (int)floor((mx + h) / bw);
+                // block b's links reach [4bh - h/2, 4bh + 4.5h]
+                lo[a] = (int)floor((mn - 4.5 * h) / bw);
+                hi[a] = (int)floor((mx + 0.5 * h) / bw);
                 lo[a] = lo[a] < 0 ? 0 : lo[a];
                 hi[a] = hi[a] > nb[a] - 1 ? nb[a] - 1 : hi[a];
             }
@@ -477,9 +477,10 @@ __global__ void __launch_bounds__(64) k_links_pass1(DevMesh m, DevLevel d, int32
                 const int bx = lo[0] + it % sx, by = lo[1] + (it / sx) % sy, bz = lo[2] + it / (sx * sy);
                 const int idx = forest_lookup(d, bx, by, bz);
                 if (idx >= 0) {
-                    // widened box [4bh - h, 4(b+1)h + h], plus a relative margin
+                    // box [4bh - h/2, 4(b+1)h + h/2] reached by the block's links,
+                    // plus a relative margin
                     const double c[3] = {(bx + 0.5) * bw, (by + 0.5) * bw, (bz + 0.5) * bw};
-                    const double hs = (0.5 * bw + h) * (1.0 + 1e-9);
+                    const double hs = (0.5 * bw + 0.5 * h) * (1.0 + 1e-9);
                     has = tri_box_overlap(c, hs, v[0], v[1], v[2]);
                     key = idx;
                 }

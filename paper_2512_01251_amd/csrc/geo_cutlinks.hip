@@ -101,10 +101,18 @@ __device__ __forceinline__ uint32_t block_link_mask(const DevLevel& d, const int
 }
 
 __global__ void __launch_bounds__(64) k_cl_mask(DevLevel d, const int32_t* off, const int32_t* val, int64_t cap,
-                                                int lattice, uint32_t* link_mask, int32_t* blk_cnt) {
+                                                const int32_t* loff, int lattice, uint32_t* link_mask,
+                                                int32_t* blk_cnt) {
     __shared__ unsigned halo[36];
     const uint32_t dirs = lattice_dirs(lattice);
     for (int64_t b = blockIdx.x; b < d.nblocks; b += gridDim.x) {
+        // a cut link crosses the surface inside the block's reach, so a block
+        // without candidate triangles has none (uniform branch)
+        if (loff[b] == loff[b + 1]) {
+            if (link_mask) link_mask[64 * b + threadIdx.x] = 0;
+            if (threadIdx.x == 0) blk_cnt[b] = 0;
+            continue;
+        }
         const uint32_t m = block_link_mask(d, off, val, cap, dirs, b, halo);
         if (link_mask) link_mask[64 * b + threadIdx.x] = m;
         int c = __popc(m);
@@ -483,7 +491,7 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
     __shared__ unsigned halo[36];
     __shared__ uint8_t plist[64 * CL_MAXC];   // per link: box-passing candidate slots
     __shared__ int ppre[65];                  // prefix of the per-link counts
-    __shared__ unsigned long long pkey[64 * CL_MAXC];  // phase-2 results
+    __shared__ unsigned long long lbest[64];  // nearest hit of each lane's link (packed key)
     __shared__ int sk[64];                    // link (t, k) of each lane, packed t | k << 8
     const int L = d.level;
     const int lane = threadIdx.x;
@@ -553,7 +561,7 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
         const float shi[3] = {(float)geo_max(t & 3, (t & 3) + cx), (float)geo_max((t >> 2) & 3, ((t >> 2) & 3) + cy),
                               (float)geo_max(t >> 4, (t >> 4) + cz)};
         const int64_t lbase = (int64_t)blk_off[b] + lchunk * 64;
-        unsigned long long best = KEY_MISS;
+        lbest[lane] = KEY_MISS;
         int ci = 0;
         while (ci < nstage) {  // uniform
             // phase 1: box tests, each lane lists its passing candidates
@@ -613,16 +621,11 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
                         if (qi < cap) fixq[qi] = (int32_t)pos;
                     }
                 }
-                pkey[p] = kk;
-            }
-            __syncthreads();
-            // phase 3: each link keeps its nearest hit
-            for (int j = 0; j < cnt; j++) {
-                const unsigned long long kk = pkey[ppre[lane] + j];
-                best = kk < best ? kk : best;
+                if (kk != KEY_MISS) atomicMin(&lbest[ow], kk);  // each link keeps its nearest hit
             }
             __syncthreads();
         }
+        const unsigned long long best = lbest[lane];
         if (active) {
             const int64_t pos = lbase + lane;
             if (pos < cap) {
@@ -729,7 +732,7 @@ int launch_cutlinks(const DevMesh& m, const DevLevel& d, const geo_bins* rows, c
     int32_t* fixn = reinterpret_cast<int32_t*>(p);
     if (nb == 0) return geo_fill_u64(reinterpret_cast<uint64_t*>(d_nlinks), 0, 1, s);
     const unsigned g = (unsigned)(nb < 262144 ? nb : 262144);
-    k_cl_mask<<<g, 64, 0, s>>>(d, rows->off, rows->val, rows->cap, lattice, link_mask, blk_cnt);
+    k_cl_mask<<<g, 64, 0, s>>>(d, rows->off, rows->val, rows->cap, links->off, lattice, link_mask, blk_cnt);
     GEO_LAUNCH_CHECK();
     int rc = geo_scan_exclusive(blk_cnt, blk_off, nb, partials, s);
     if (rc != GEO_OK) return rc;
