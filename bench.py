@@ -147,7 +147,7 @@ def main():
         "mcells_per_s_voxelize": cells / (vox / 1e3) / 1e6 if vox else None,
         "mlinks_per_s": n_links / (lnk / 1e3) / 1e6 if lnk else None,
         "call_ms_f32": {k: round(v, 4) for k, v in calls32.items()},
-        "stats_f32": dict(zip(["f32_to_f64", "exact", "links_exact", "contract", "staged", "pairs"], stats)),
+        "stats_f32": dict(zip(["f32_to_f64", "exact", "links_exact", "contract", "staged", "pairs", "tasks"], stats)),
         **res64,
     }
     if not args.no_cpu_baseline:

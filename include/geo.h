@@ -72,7 +72,8 @@ enum {
     GEO_STAT_CONTRACT = 3,   /* vertex coordinates outside the documented range     */
     GEO_STAT_STAGED = 4,     /* candidate triangles staged by the q kernel          */
     GEO_STAT_PAIRS = 5,      /* (link, candidate) pairs passing the box test        */
-    GEO_NSTATS = 6
+    GEO_STAT_TASKS = 6,      /* (64 links x 64 candidates) tasks of the q kernel     */
+    GEO_NSTATS = 7
 };
 
 #define GEO_MAX_LEVELS 12

@@ -21,7 +21,8 @@ GEO_PREC_F64, GEO_PREC_F32_FALLBACK = 0, 1
 GEO_BINS_ROWS, GEO_BINS_LINKS = 0, 1
 GEO_CALL_BINS_ROWS, GEO_CALL_BINS_LINKS, GEO_CALL_REFINE, GEO_CALL_CUTLINKS = 0, 1, 2, 3
 GEO_STAT_F32_TO_F64, GEO_STAT_EXACT, GEO_STAT_LINKS_EXACT, GEO_STAT_CONTRACT, GEO_STAT_STAGED, GEO_STAT_PAIRS = 0, 1, 2, 3, 4, 5
-GEO_NSTATS = 6
+GEO_STAT_TASKS = 6
+GEO_NSTATS = 7
 GEO_MAX_LEVELS = 12
 GEO_MAX_RES = 32767
 

@@ -261,7 +261,7 @@ __device__ void stage_cand(const DevMesh& m, int L, int tri, const int b0[3], Ca
 }
 
 struct QStats {
-    unsigned fb = 0, ex = 0, tq = 0, staged = 0, pairs = 0;
+    unsigned fb = 0, ex = 0, tq = 0, staged = 0, pairs = 0, tasks = 0;
 };
 
 // sign of orient3d with float64 filter then exact arithmetic
@@ -490,7 +490,7 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
     __shared__ int spre[65];
     __shared__ unsigned halo[36];
     __shared__ uint8_t plist[64 * CL_MAXC];   // per link: box-passing candidate slots
-    __shared__ int ppre[65];                  // prefix of the per-link counts
+    __shared__ uint16_t flat[64 * CL_MAXC];   // flattened pairs: owner lane | candidate slot << 6
     __shared__ unsigned long long lbest[64];  // nearest hit of each lane's link (packed key)
     __shared__ int sk[64];                    // link (t, k) of each lane, packed t | k << 8
     const int L = d.level;
@@ -516,6 +516,7 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
         const int local = task - task_off[b];
         const int lchunk = local / ncc, cchunk = local % ncc;
         const int b0[3] = {4 * d.bcoord[3 * b], 4 * d.bcoord[3 * b + 1], 4 * d.bcoord[3 * b + 2]};
+        st.tasks++;
         if (b != b_prev) {  // uniform
             const uint32_t mk = block_link_mask(d, roff, rval, rcap, dirs, b, halo);
             smask[lane] = mk;
@@ -580,21 +581,16 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
                 const int tt = __shfl_up(inc2, o, 64);
                 if (lane >= o) inc2 += tt;
             }
-            ppre[lane] = inc2 - cnt;
-            if (lane == 63) ppre[64] = inc2;
+            const int pbase = inc2 - cnt;
+            for (int j = 0; j < cnt; j++) flat[pbase + j] = (uint16_t)(lane | (plist[lane * CL_MAXC + j] << 6));
+            const int P = __shfl(inc2, 63, 64);
             __syncthreads();
-            const int P = ppre[64];
             st.pairs += cnt;
             // phase 2: one pair per lane
             for (int p = lane; p < P; p += 64) {
-                int lo = 0, hi = 63;  // owner: largest l with ppre[l] <= p
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (ppre[mid] <= p) lo = mid;
-                    else hi = mid - 1;
-                }
-                const int ow = lo;
-                const int cidx = plist[ow * CL_MAXC + (p - ppre[ow])];
+                const int fe = flat[p];
+                const int ow = fe & 63;
+                const int cidx = fe >> 6;
                 const int tk = sk[ow];
                 const int ot = tk & 0xff, ok = tk >> 8;
                 int ox, oy, oz;
@@ -641,6 +637,7 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
         wave_count(&stats[GEO_STAT_F32_TO_F64], st.fb);
         wave_count(&stats[GEO_STAT_STAGED], st.staged);
         wave_count(&stats[GEO_STAT_PAIRS], st.pairs);
+        if (threadIdx.x == 0 && st.tasks) atomicAdd((unsigned long long*)&stats[GEO_STAT_TASKS], (unsigned long long)st.tasks);
     }
 }
 
