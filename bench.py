@@ -10,13 +10,16 @@ the next level is inside it.
 Prints one JSON line.  value = cells voxelized per second over the whole
 step (all levels, float32 form with float64/exact fallback); the extra
 fields give the voxelization-only and link-only rates, the float64 form and
-the speedup, per-call times, the roofline of the dominant kernel and the
-CPU oracle timed on a bounded sample of the same workload.
+the speedup, per-call and per-kernel times, the roofline of the dominant
+kernel (the cut-link q kernel) and the CPU oracle timed on a bounded sample
+of the same workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -26,8 +29,17 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+# MI355X published peak: float32 vector (packed) 157.3 TFLOP/s
 FP32_PEAK_TFLOPS = 157.3
+# algorithmic work of the q kernel (floating-point operations):
+#   per (cell with a link, candidate triangle of its block): plane side of the cell centre
+#   per (link, candidate triangle of its block): plane side of the far end, crossing
+#   parameter, three edge functions at the crossing
+FLOP_PER_CELL_CAND = 6
+FLOP_PER_LINK_CAND = 25
+PMC_PROFILE = os.path.join(ROOT, "profiles", "k_cl_q_star7m_pmc.txt")
+Q_KERNEL_SOURCES = [os.path.join(ROOT, "paper_2512_01251_amd", "csrc", f)
+                    for f in ("geo_cutlinks.hip", "geo_internal.h")]
 
 
 def _sync():
@@ -36,17 +48,28 @@ def _sync():
 
 
 def run_steps(emb, V, T, w, precision, steps):
-    import torch
+    """Times `steps` whole steps; returns (mean s/step, 95% half-width s, output)."""
     _sync()
+    dts = []
     t0 = time.perf_counter()
     for _ in range(steps):
+        ts = time.perf_counter()
         out = emb.embed(V, T, w.n0, w.lf, w.lattice, w.d_spec, precision)
+        dts.append(time.perf_counter() - ts)
     _sync()
-    return (time.perf_counter() - t0) / steps, out
+    mean = (time.perf_counter() - t0) / steps
+    ci = 1.96 * float(np.std(dts, ddof=1)) / math.sqrt(steps) if steps > 1 else None
+    return mean, ci, out
 
 
 def call_times(emb, V, T, w, precision, reps=3):
-    """Per-call device times (ms) from events around each C call, averaged."""
+    """Per-call device times (ms) from events around each C call, and per-kernel
+    device times (ms per launch) from the library's kernel timer, averaged."""
+    import paper_2512_01251_amd as geo
+    kernels = {"k_rows_pass1": geo.GEO_KT_ROWS, "k_voxelize": geo.GEO_KT_VOXELIZE,
+               "k_links_pass1": geo.GEO_KT_LINKS_BINS, "k_cl_q": geo.GEO_KT_CUTLINKS_Q}
+    for k in kernels.values():
+        geo.geo_kernel_timer(k, True)
     agg = {}
     for _ in range(reps):
         emb.events = []
@@ -55,58 +78,122 @@ def call_times(emb, V, T, w, precision, reps=3):
         for name, s, e in emb.events:
             agg[name] = agg.get(name, 0.0) + s.elapsed_time(e) / reps
         emb.events = None
-    return agg, out
+    kms = {}
+    for name, k in kernels.items():
+        ms, n = geo.geo_kernel_timer_read(k)
+        geo.geo_kernel_timer(k, False)
+        kms[name] = {"ms_per_launch": round(ms / n, 4) if n else None, "launches_per_step": n // reps}
+    return agg, kms, out
 
 
-def cpu_baseline(w, out, seconds=15.0):
-    """The oracle (as it stands) on a bounded random sample of the finest
-    level's cells and links of the same workload."""
+def q_kernel_units(out):
+    """Units of algorithmic work of one q-kernel launch: (link, candidate) and
+    (cell with a link, candidate) pairs, candidates = the LINKS bin of the block."""
+    import torch
+    lv = out.levels[-1]
+    nb = int(lv.bcoord.shape[0])
+    cell = out.links.cell.long()
+    nl = torch.bincount(cell // 64, minlength=nb)
+    ucell = torch.unique_consecutive(cell)
+    nce = torch.bincount(ucell // 64, minlength=nb)
+    off = out.links.bins_off.long()
+    nc = off[1:nb + 1] - off[:nb]
+    return int((nl * nc).sum()), int((nce * nc).sum())
+
+
+def q_kernel_traffic():
+    """HBM bytes per launch of the q kernel from the committed counter profile,
+    or None when the kernel's sources changed since the counters were taken."""
+    if not os.path.exists(PMC_PROFILE):
+        return None, "no counter profile"
+    h = hashlib.sha256()
+    for p in Q_KERNEL_SOURCES:
+        h.update(open(p, "rb").read())
+    fields = {}
+    for line in open(PMC_PROFILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("source_sha256") != h.hexdigest():
+        return None, "kernel changed since the counters were taken"
+    return float(fields["traffic_bytes_per_launch"]), "FETCH_SIZE + WRITE_SIZE, copy-calibrated"
+
+
+def cpu_baseline(w, out, n_blocks=60000, with_links=False, n_links=20000):
+    """The oracle (as it stands) on a bounded random sample of the same
+    workload: every cell of n_blocks blocks drawn uniformly from the blocks of
+    all levels (point classification, including the oracle's bucket build)."""
     import oracle
     rng = np.random.default_rng(0)
-    lv = out.levels[-1]
-    bc = lv.bcoord.cpu().numpy()
-    L = lv.level
-    nb = len(bc)
-    n_cells = 20000
-    b = rng.integers(0, nb, n_cells)
-    t = rng.integers(0, 64, n_cells)
-    cells = 4 * bc[b] + np.stack([t & 3, (t >> 2) & 3, t >> 4], 1)
-    pts = (cells + 0.5) * 2.0 ** -L
+    counts = np.array([lv.bcoord.shape[0] for lv in out.levels])
+    lvl = rng.choice(len(counts), n_blocks, p=counts / counts.sum())
+    pts = []
+    t = np.arange(64)
+    tc = np.stack([t & 3, (t >> 2) & 3, t >> 4], 1)
+    for L, lv in enumerate(out.levels):
+        k = int((lvl == L).sum())
+        if k == 0:
+            continue
+        bc = lv.bcoord.cpu().numpy()
+        b = rng.integers(0, len(bc), k)
+        cells = (4 * bc[b])[:, None, :] + tc[None]
+        pts.append(((cells + 0.5) * 2.0 ** -L).reshape(-1, 3))
+    pts = np.concatenate(pts)
     t0 = time.perf_counter()
     oracle.solid_points(w.mesh, w.n0, pts)
-    tc = time.perf_counter() - t0
-    nl = out.links.n
-    n_links = min(4000, nl)
-    li = rng.integers(0, nl, n_links)
-    lc = out.links.cell.cpu().numpy()[li]
-    lb, lt = lc // 64, lc % 64
-    lcells = 4 * bc[lb] + np.stack([lt & 3, (lt >> 2) & 3, lt >> 4], 1)
-    t0 = time.perf_counter()
-    oracle.q_points(w.mesh, w.n0, L, lcells, out.links.dir.cpu().numpy()[li])
-    tl = time.perf_counter() - t0
-    return {"value": n_cells / tc / 1e6, "unit": "Mcells/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "mlinks_per_s": n_links / tl / 1e6,
-            "sample": f"{n_cells} random finest-level cells (point classification incl. bucket build) "
-                      f"and {n_links} random links (nearest hit) of the same workload"}
+    tc_s = time.perf_counter() - t0
+    res = {"value": len(pts) / tc_s / 1e6, "unit": "Mcells/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "seconds": tc_s,
+           "sample": f"all 64 cells of {n_blocks} blocks drawn uniformly from the blocks of levels 0..{len(counts) - 1} "
+                     f"({len(pts)} cells; exact point classification, bucket build included)"}
+    if with_links:
+        lv = out.levels[-1]
+        bc = lv.bcoord.cpu().numpy()
+        li = rng.integers(0, out.links.n, min(n_links, out.links.n))
+        lc = out.links.cell.cpu().numpy()[li]
+        lcells = 4 * bc[lc // 64] + tc[lc % 64]
+        t0 = time.perf_counter()
+        oracle.q_points(w.mesh, w.n0, lv.level, lcells, out.links.dir.cpu().numpy()[li])
+        tl = time.perf_counter() - t0
+        res["mlinks_per_s"] = len(li) / tl / 1e6
+        res["links_sample"] = f"{len(li)} random links of the table (nearest hit, bucket build included)"
+    return res
+
+
+def copy_probe(nbytes=1 << 30, reps=3):
+    """A plain device copy of known size, for calibrating HBM byte counters."""
+    import torch
+    x = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    _sync()
+    print(f"[bench] copy probe: {reps} copies of {nbytes} bytes", file=sys.stderr, flush=True)
+    del x, y
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="star7m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-links", action="store_true", help="also time the oracle's q on a link sample")
     ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB device copy first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU sharding is a design "
-                                   "(spatial slabs along z), not an implementation"}))
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the multi-GPU sharding "
+              "is a design (slabs of base blocks along z), not an implementation", file=sys.stderr)
         sys.exit(2)
     import torch
+    import paper_2512_01251_amd as geo
     from synth import configs
     from paper_2512_01251_amd.pipeline import Embedder
 
+    if args.copy_probe:
+        copy_probe()
     w = configs.get(args.workload)
     V = torch.from_numpy(np.ascontiguousarray(w.mesh.verts)).cuda()
     T = torch.from_numpy(np.ascontiguousarray(w.mesh.tris)).cuda()
@@ -114,23 +201,33 @@ def main():
     for _ in range(args.warmup):
         emb.embed(V, T, w.n0, w.lf, w.lattice, w.d_spec, "f32")
     print(f"[bench] warmup done ({args.workload})", file=sys.stderr, flush=True)
-    t32, out = run_steps(emb, V, T, w, "f32", args.steps)
+    geo.geo_kernel_timer(geo.GEO_KT_CUTLINKS_Q, True)
+    t32, ci32, out = run_steps(emb, V, T, w, "f32", args.steps)
+    q_ms, q_n = geo.geo_kernel_timer_read(geo.GEO_KT_CUTLINKS_Q)
+    geo.geo_kernel_timer(geo.GEO_KT_CUTLINKS_Q, False)
     print(f"[bench] f32 {t32*1e3:.2f} ms/step", file=sys.stderr, flush=True)
     cells = sum(64 * lv.bcoord.shape[0] for lv in out.levels)
     n_links = out.links.n
-    calls32, _ = call_times(emb, V, T, w, "f32")
+    calls32, kern32, _ = call_times(emb, V, T, w, "f32")
     res64 = {}
     if not args.no_f64:
         for _ in range(args.warmup):
             emb.embed(V, T, w.n0, w.lf, w.lattice, w.d_spec, "f64")
-        t64, _ = run_steps(emb, V, T, w, "f64", args.steps)
+        t64, ci64, _ = run_steps(emb, V, T, w, "f64", args.steps)
         print(f"[bench] f64 {t64*1e3:.2f} ms/step", file=sys.stderr, flush=True)
-        calls64, _ = call_times(emb, V, T, w, "f64")
-        res64 = {"ms_per_step_f64": t64 * 1e3, "speedup_step_f32_vs_f64": t64 / t32,
-                 "call_ms_f64": {k: round(v, 4) for k, v in calls64.items()}}
+        calls64, kern64, _ = call_times(emb, V, T, w, "f64")
+        res64 = {"ms_per_step_f64": t64 * 1e3, "ms_per_step_f64_ci95": ci64 * 1e3 if ci64 else None,
+                 "speedup_step_f32_vs_f64": t64 / t32,
+                 "call_ms_f64": {k: round(v, 4) for k, v in calls64.items()}, "kernel_ms_f64": kern64}
+    vox_only = sum(v for k, v in calls32.items() if k.startswith("voxelize"))
     vox = sum(v for k, v in calls32.items() if k.startswith("rows") or k.startswith("voxelize"))
     lnk = calls32.get("linkbins", 0.0) + calls32.get("cutlinks", 0.0)
     stats = out.stats.cpu().numpy().tolist()
+    p_link, p_cell = q_kernel_units(out)
+    flop = FLOP_PER_LINK_CAND * p_link + FLOP_PER_CELL_CAND * p_cell
+    q_launch_ms = q_ms / q_n if q_n else float("nan")
+    achieved = flop / (q_launch_ms * 1e-3) / 1e12
+    traffic, traffic_src = q_kernel_traffic()
     line = {
         "metric": "Mcells/s voxelized + Mlinks/s q at 7.2M tris; FP32+fallback vs FP64 speedup",
         "value": cells / t32 / 1e6,
@@ -142,16 +239,26 @@ def main():
         "config": {"workload": w.name, "triangles": w.mesh.nt, "vertex_dtype": str(w.mesh.verts.dtype),
                    "base_grid": list(w.n0), "levels": w.lf + 1, "lattice": f"D3Q{w.lattice}",
                    "d_spec": w.d_spec},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
+                     "kernel": "k_cl_q<float>", "launch_ms": q_launch_ms, "launches": q_n,
+                     "flop_per_launch": flop, "link_cand_pairs": p_link, "cell_cand_pairs": p_cell,
+                     "traffic_source": traffic_src},
+        "ms_per_step_ci95": ci32 * 1e3 if ci32 else None,
         "cells": cells, "links": n_links,
         "blocks_per_level": [int(lv.bcoord.shape[0]) for lv in out.levels],
-        "mcells_per_s_voxelize": cells / (vox / 1e3) / 1e6 if vox else None,
-        "mlinks_per_s": n_links / (lnk / 1e3) / 1e6 if lnk else None,
+        "mcells_per_s_voxelize": cells / (vox_only / 1e3) / 1e6 if vox_only else None,
+        "mcells_per_s_rows_voxelize": cells / (vox / 1e3) / 1e6 if vox else None,
+        "mlinks_per_s": n_links / (calls32["cutlinks"] / 1e3) / 1e6 if calls32.get("cutlinks") else None,
+        "mlinks_per_s_with_bins": n_links / (lnk / 1e3) / 1e6 if lnk else None,
         "call_ms_f32": {k: round(v, 4) for k, v in calls32.items()},
+        "kernel_ms_f32": kern32,
         "stats_f32": dict(zip(["f32_to_f64", "exact", "links_exact", "contract", "staged", "pairs", "tasks"], stats)),
         **res64,
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w, out)
+        print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(w, out, with_links=args.cpu_links)
     print(json.dumps(line), flush=True)
 
 

@@ -211,6 +211,33 @@ int geo_cutlinks_backward(const geo_mesh* mesh, const geo_level* lv, int64_t n_l
                           const int32_t* link_tri, const float* grad_q, float* grad_verts,
                           geo_stream_t stream);
 
+/*
+ * Kernel timer (measurement only; it changes nothing that is computed).
+ * While enabled for a kernel, every launch of that kernel is bracketed by two
+ * HIP events recorded on the stream the kernel is launched on, so one
+ * kernel's device time can be read inside a call that launches several.
+ * geo_kernel_timer(kernel, enable) switches it on (non-zero) or off and
+ * forgets unread launches.  geo_kernel_timer_read waits for the recorded
+ * events and returns the summed duration in ms and the number of timed
+ * launches since the timer was enabled or last read, then starts over.  At
+ * most GEO_KT_MAX_LAUNCHES launches are kept between reads; later ones are
+ * not timed.  Events are created on the device current at a kernel's first
+ * timed launch and are kept for reuse until the process ends.  This switch
+ * and its events are the library's only host-side state (process-wide,
+ * guarded by a mutex).  Returns GEO_ERR_ARG for an unknown kernel or NULL
+ * outputs, GEO_ERR_DEVICE if an event wait fails.
+ */
+enum {
+    GEO_KT_ROWS = 0,       /* ROWS bins, triangle pass (count / append)          */
+    GEO_KT_VOXELIZE = 1,   /* solid voxelization of one level                   */
+    GEO_KT_LINKS_BINS = 2, /* LINKS bins, triangle pass (block overlap tests)    */
+    GEO_KT_CUTLINKS_Q = 3, /* cut-link q kernel (nearest hit per link)          */
+    GEO_KT_COUNT = 4
+};
+#define GEO_KT_MAX_LAUNCHES 4096
+int geo_kernel_timer(int32_t kernel, int32_t enable);
+int geo_kernel_timer_read(int32_t kernel, double* total_ms, int64_t* launches);
+
 const char* geo_version(void);
 
 #ifdef __cplusplus

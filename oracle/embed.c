@@ -75,6 +75,13 @@ static void buckets_build(buckets* B, int dim, const double* V, const int32_t* T
     for (int a = 0; a < 3; a++) B->nb[a] = 1;
     for (int a = ax0; a < 3; a++) B->nb[a] = (int)ceil(n0[a] / s) + 1;
     int64_t nbk = (int64_t)B->nb[0] * B->nb[1] * B->nb[2];
+    /* a surface fills few cells of a 3D grid: keep the grid to 2^25 buckets */
+    while (dim == 3 && nbk > ((int64_t)1 << 25)) {
+        s *= 2.0;
+        B->s = s;
+        for (int a = ax0; a < 3; a++) B->nb[a] = (int)ceil(n0[a] / s) + 1;
+        nbk = (int64_t)B->nb[0] * B->nb[1] * B->nb[2];
+    }
     int64_t* cnt = (int64_t*)calloc(nbk + 1, sizeof(int64_t));
     int lo[3], hi[3];
     for (int pass = 0; pass < 2; pass++) {

@@ -23,11 +23,13 @@ GEO_CALL_BINS_ROWS, GEO_CALL_BINS_LINKS, GEO_CALL_REFINE, GEO_CALL_CUTLINKS = 0,
 GEO_STAT_F32_TO_F64, GEO_STAT_EXACT, GEO_STAT_LINKS_EXACT, GEO_STAT_CONTRACT, GEO_STAT_STAGED, GEO_STAT_PAIRS = 0, 1, 2, 3, 4, 5
 GEO_STAT_TASKS = 6
 GEO_NSTATS = 7
+GEO_KT_ROWS, GEO_KT_VOXELIZE, GEO_KT_LINKS_BINS, GEO_KT_CUTLINKS_Q, GEO_KT_COUNT = 0, 1, 2, 3, 4
+GEO_KT_MAX_LAUNCHES = 4096
 GEO_MAX_LEVELS = 12
 GEO_MAX_RES = 32767
 
 EXPORTS = ["geo_workspace_size", "geo_nprop", "geo_level0_blocks", "geo_build_bins", "geo_voxelize",
-           "geo_refine_flags", "geo_cutlinks", "geo_cutlinks_backward", "geo_version"]
+           "geo_refine_flags", "geo_cutlinks", "geo_cutlinks_backward", "geo_kernel_timer", "geo_kernel_timer_read", "geo_version"]
 
 
 class GeoError(RuntimeError):
@@ -71,6 +73,8 @@ def lib():
         L.geo_refine_flags.argtypes = [LP, P, i32, P, P, P, P, P, P, sz, P]
         L.geo_cutlinks.argtypes = [MP, LP, BP, BP, i32, i32, P, i64, P, P, P, P, P, P, P, sz, P]
         L.geo_cutlinks_backward.argtypes = [MP, LP, i64, P, P, P, P, P, P]
+        L.geo_kernel_timer.argtypes = [i32, i32]
+        L.geo_kernel_timer_read.argtypes = [i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.geo_version.restype = C.c_char_p
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype or C.c_int
@@ -137,6 +141,17 @@ def geo_nprop(d_spec: float) -> int:
 
 def geo_version() -> str:
     return lib().geo_version().decode()
+
+
+def geo_kernel_timer(kernel: int, enable: bool):
+    _check(lib().geo_kernel_timer(int(kernel), 1 if enable else 0), "geo_kernel_timer")
+
+
+def geo_kernel_timer_read(kernel: int):
+    """(summed duration in ms, number of timed launches) since the last read."""
+    ms, n = C.c_double(0.0), C.c_int64(0)
+    _check(lib().geo_kernel_timer_read(int(kernel), C.byref(ms), C.byref(n)), "geo_kernel_timer_read")
+    return ms.value, n.value
 
 
 def geo_level0_blocks(n0, bcoord, stream=None):

@@ -527,10 +527,12 @@ int launch_rows_pass1(const DevMesh& m, const DevLevel& d, int precision, int32_
                       int64_t cap, int64_t* d_count, uint64_t* d_stats, hipStream_t s) {
     if (m.nt == 0) return GEO_OK;
     const unsigned g = grid_for(m.nt, 64, 16384);
+    kt_record(GEO_KT_ROWS, s, false);
     if (precision == GEO_PREC_F32_FALLBACK)
         k_rows_pass1<float><<<g, 64, 0, s>>>(m, d, cnt, pairs, cap, d_count, d_stats);
     else
         k_rows_pass1<double><<<g, 64, 0, s>>>(m, d, cnt, pairs, cap, d_count, d_stats);
+    kt_record(GEO_KT_ROWS, s, true);
     GEO_LAUNCH_CHECK();
     return GEO_OK;
 }
@@ -538,7 +540,9 @@ int launch_rows_pass1(const DevMesh& m, const DevLevel& d, int precision, int32_
 int launch_links_pass1(const DevMesh& m, const DevLevel& d, int32_t* cnt, int2* pairs, int64_t cap,
                        int64_t* d_count, hipStream_t s) {
     if (m.nt == 0) return GEO_OK;
+    kt_record(GEO_KT_LINKS_BINS, s, false);
     k_links_pass1<<<grid_for(m.nt, 64, 16384), 64, 0, s>>>(m, d, cnt, pairs, cap, d_count);
+    kt_record(GEO_KT_LINKS_BINS, s, true);
     GEO_LAUNCH_CHECK();
     return GEO_OK;
 }

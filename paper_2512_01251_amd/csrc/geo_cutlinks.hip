@@ -744,6 +744,7 @@ int launch_cutlinks(const DevMesh& m, const DevLevel& d, const geo_bins* rows, c
         GEO_LAUNCH_CHECK();
     }
     const unsigned gq = 16384;
+    kt_record(GEO_KT_CUTLINKS_Q, s, false);
     if (precision == GEO_PREC_F32_FALLBACK)
         k_cl_q<float><<<gq, 64, 0, s>>>(m, d, rows->off, rows->val, rows->cap, links->off, links->val, links->cap,
                                         lattice, blk_off, task_off, cap, link_cell, link_dir, keys, mark, fixq, fixn,
@@ -752,6 +753,7 @@ int launch_cutlinks(const DevMesh& m, const DevLevel& d, const geo_bins* rows, c
         k_cl_q<double><<<gq, 64, 0, s>>>(m, d, rows->off, rows->val, rows->cap, links->off, links->val, links->cap,
                                          lattice, blk_off, task_off, cap, link_cell, link_dir, keys, mark, fixq, fixn,
                                          d_stats);
+    kt_record(GEO_KT_CUTLINKS_Q, s, true);
     GEO_LAUNCH_CHECK();
     if (cap > 0) {
         k_cl_fix<<<4096, 64, 0, s>>>(m, d, links->off, links->val, links->cap, link_cell, link_dir, fixq, fixn, cap,

@@ -255,6 +255,10 @@ __device__ __forceinline__ void wave_count(uint64_t* ctr, unsigned n) {
 // --------------------------------------------------------------------------
 // host-side launchers (defined in the .hip files)
 // --------------------------------------------------------------------------
+// records the start (stop = false) or stop event of a timed launch when the
+// kernel timer is on for that kernel (no-op otherwise)
+void kt_record(int kernel, hipStream_t s, bool stop);
+
 int geo_scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* partials,
                        hipStream_t s);
 size_t geo_scan_partials_bytes(int64_t n);

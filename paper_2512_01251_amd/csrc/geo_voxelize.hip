@@ -93,7 +93,9 @@ int launch_voxelize(const DevLevel& d, const int32_t* off, const int32_t* val, i
     int64_t waves = (d.nblocks + 3) / 4;
     int64_t g = (waves * 64 + 255) / 256;
     if (g > 65536) g = 65536;
+    kt_record(GEO_KT_VOXELIZE, s, false);
     k_voxelize<<<(unsigned)g, 256, 0, s>>>(d, off, val, cap, solid);
+    kt_record(GEO_KT_VOXELIZE, s, true);
     GEO_LAUNCH_CHECK();
     return GEO_OK;
 }

@@ -188,3 +188,16 @@ def test_float_filters_certify_most_random_cases(hp):
         cert64 += hp.hp_orient3d_filter_f64(*ptr) != 0
         cert32 += hp.hp_orient3d_filter_f32(*ptr) != 0
     assert cert64 == 2000 and cert32 > 1900
+
+
+def test_kernel_timer_host_side(geo):
+    # switching and reading with nothing launched touches no device
+    assert geo.lib().geo_kernel_timer(geo.GEO_KT_COUNT, 1) == geo.GEO_ERR_ARG
+    assert geo.lib().geo_kernel_timer(-1, 1) == geo.GEO_ERR_ARG
+    for k in range(geo.GEO_KT_COUNT):
+        geo.geo_kernel_timer(k, True)
+        assert geo.geo_kernel_timer_read(k) == (0.0, 0)
+        geo.geo_kernel_timer(k, False)
+    import ctypes as C
+    assert geo.lib().geo_kernel_timer_read(0, None, None) == geo.GEO_ERR_ARG
+    assert geo.lib().geo_kernel_timer_read(7, C.byref(C.c_double()), C.byref(C.c_int64())) == geo.GEO_ERR_ARG
