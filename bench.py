@@ -119,36 +119,43 @@ def q_kernel_traffic():
     return float(fields["traffic_bytes_per_launch"]), "FETCH_SIZE + WRITE_SIZE, copy-calibrated"
 
 
-def cpu_baseline(w, out, n_blocks=60000, with_links=False, n_links=20000):
+def cpu_baseline(w, out, chunk_blocks=120000, min_seconds=10.0, max_chunks=16, with_links=False,
+                 n_links=20000):
     """The oracle (as it stands) on a bounded random sample of the same
-    workload: every cell of n_blocks blocks drawn uniformly from the blocks of
-    all levels (point classification, including the oracle's bucket build)."""
+    workload: chunks of every cell of chunk_blocks blocks drawn uniformly from
+    the blocks of all levels (exact point classification, the oracle's bucket
+    build included in every chunk), until min_seconds of CPU work."""
     import oracle
     rng = np.random.default_rng(0)
     counts = np.array([lv.bcoord.shape[0] for lv in out.levels])
-    lvl = rng.choice(len(counts), n_blocks, p=counts / counts.sum())
-    pts = []
+    bcs = [lv.bcoord.cpu().numpy() for lv in out.levels]
     t = np.arange(64)
     tc = np.stack([t & 3, (t >> 2) & 3, t >> 4], 1)
-    for L, lv in enumerate(out.levels):
-        k = int((lvl == L).sum())
-        if k == 0:
-            continue
-        bc = lv.bcoord.cpu().numpy()
-        b = rng.integers(0, len(bc), k)
-        cells = (4 * bc[b])[:, None, :] + tc[None]
-        pts.append(((cells + 0.5) * 2.0 ** -L).reshape(-1, 3))
-    pts = np.concatenate(pts)
-    t0 = time.perf_counter()
-    oracle.solid_points(w.mesh, w.n0, pts)
-    tc_s = time.perf_counter() - t0
-    res = {"value": len(pts) / tc_s / 1e6, "unit": "Mcells/s", "cores": oracle.num_threads(), "kind": "oracle",
-           "seconds": tc_s,
-           "sample": f"all 64 cells of {n_blocks} blocks drawn uniformly from the blocks of levels 0..{len(counts) - 1} "
-                     f"({len(pts)} cells; exact point classification, bucket build included)"}
+    n_pts, secs, chunks = 0, 0.0, 0
+    while secs < min_seconds and chunks < max_chunks:
+        lvl = rng.choice(len(counts), chunk_blocks, p=counts / counts.sum())
+        pts = []
+        for L, bc in enumerate(bcs):
+            k = int((lvl == L).sum())
+            if k == 0:
+                continue
+            b = rng.integers(0, len(bc), k)
+            cells = (4 * bc[b])[:, None, :] + tc[None]
+            pts.append(((cells + 0.5) * 2.0 ** -L).reshape(-1, 3))
+        pts = np.concatenate(pts)
+        t0 = time.perf_counter()
+        oracle.solid_points(w.mesh, w.n0, pts)
+        secs += time.perf_counter() - t0
+        n_pts += len(pts)
+        chunks += 1
+    res = {"value": n_pts / secs / 1e6, "unit": "Mcells/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "seconds": secs,
+           "sample": f"{chunks} chunks of all 64 cells of {chunk_blocks} blocks drawn uniformly from the blocks of "
+                     f"levels 0..{len(counts) - 1} ({n_pts} cells; exact point classification, bucket build "
+                     f"included in every chunk)"}
     if with_links:
         lv = out.levels[-1]
-        bc = lv.bcoord.cpu().numpy()
+        bc = bcs[-1]
         li = rng.integers(0, out.links.n, min(n_links, out.links.n))
         lc = out.links.cell.cpu().numpy()[li]
         lcells = 4 * bc[lc // 64] + tc[lc % 64]
@@ -161,14 +168,16 @@ def cpu_baseline(w, out, n_blocks=60000, with_links=False, n_links=20000):
 
 
 def copy_probe(nbytes=1 << 30, reps=3):
-    """A plain device copy of known size, for calibrating HBM byte counters."""
+    """A plain elementwise kernel of known traffic (reads nbytes, writes nbytes:
+    y = -x over float32; nothing else here negates), for calibrating the HBM
+    byte counters."""
     import torch
-    x = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
     for _ in range(reps):
-        y.copy_(x)
+        torch.neg(x, out=y)
     _sync()
-    print(f"[bench] copy probe: {reps} copies of {nbytes} bytes", file=sys.stderr, flush=True)
+    print(f"[bench] copy probe: {reps} x (read {nbytes} B, write {nbytes} B)", file=sys.stderr, flush=True)
     del x, y
 
 

@@ -392,27 +392,62 @@ __device__ __forceinline__ bool axis_sep(double p0, double p1, double p2, double
     return mn > r || mx < -r;
 }
 
-__device__ bool tri_box_overlap(const double* c, double hs, const double v0in[3], const double v1in[3],
-                                const double v2in[3]) {
+// Per-triangle quantities of the separating-axis test.
+struct SatTri {
+    double v[3][3];
+    double e[3][3];  // edges v1-v0, v2-v1, v0-v2
+    double n[3];     // e0 x e1 (rounded; any vector is a valid separating axis)
+    double nvmin, nvmax;  // min / max over the vertices of n . v
+    double nvabs;    // max over the vertices of sum_a |n_a v_a|
+    double n1;       // |n|_1
+};
+
+__device__ __forceinline__ void sat_setup(SatTri& T) {
+    for (int a = 0; a < 3; a++) {
+        T.e[0][a] = T.v[1][a] - T.v[0][a];
+        T.e[1][a] = T.v[2][a] - T.v[1][a];
+        T.e[2][a] = T.v[0][a] - T.v[2][a];
+    }
+    T.n[0] = T.e[0][1] * T.e[1][2] - T.e[0][2] * T.e[1][1];
+    T.n[1] = T.e[0][2] * T.e[1][0] - T.e[0][0] * T.e[1][2];
+    T.n[2] = T.e[0][0] * T.e[1][1] - T.e[0][1] * T.e[1][0];
+    T.nvmin = 1e300;
+    T.nvmax = -1e300;
+    T.nvabs = 0.0;
+    for (int i = 0; i < 3; i++) {
+        const double p = T.n[0] * T.v[i][0] + T.n[1] * T.v[i][1] + T.n[2] * T.v[i][2];
+        T.nvmin = fmin(T.nvmin, p);
+        T.nvmax = fmax(T.nvmax, p);
+        T.nvabs = fmax(T.nvabs, fabs(T.n[0] * T.v[i][0]) + fabs(T.n[1] * T.v[i][1]) + fabs(T.n[2] * T.v[i][2]));
+    }
+    T.n1 = fabs(T.n[0]) + fabs(T.n[1]) + fabs(T.n[2]);
+}
+
+// Conservative triangle / cube overlap (centre c, half side hs): separating
+// axes are the box normals, the triangle normal and the nine edge crosses,
+// each with a relative margin that covers the rounding of the test.
+__device__ bool tri_box_overlap(const double c[3], double hs, const SatTri& T) {
+    for (int a = 0; a < 3; a++)
+        if (axis_sep(T.v[0][a] - c[a], T.v[1][a] - c[a], T.v[2][a] - c[a], hs)) return false;
+    // the normal axis: projections n . v_i - n . c against the box radius; the
+    // margin bounds the rounding of the dot products (4.5 u each side)
+    const double nc = T.n[0] * c[0] + T.n[1] * c[1] + T.n[2] * c[2];
+    const double err = 5e-16 * (T.nvabs + fabs(T.n[0] * c[0]) + fabs(T.n[1] * c[1]) + fabs(T.n[2] * c[2]));
+    const double rn = hs * T.n1 * (1.0 + 1e-9) + 1e-12 * T.n1 + err;
+    if (T.nvmin - nc > rn || T.nvmax - nc < -rn) return false;
     double v0[3], v1[3], v2[3];
     for (int a = 0; a < 3; a++) {
-        v0[a] = v0in[a] - c[a];
-        v1[a] = v1in[a] - c[a];
-        v2[a] = v2in[a] - c[a];
+        v0[a] = T.v[0][a] - c[a];
+        v1[a] = T.v[1][a] - c[a];
+        v2[a] = T.v[2][a] - c[a];
     }
-    // box face normals
-    for (int a = 0; a < 3; a++)
-        if (axis_sep(v0[a], v1[a], v2[a], hs)) return false;
-    const double e[3][3] = {{v1[0] - v0[0], v1[1] - v0[1], v1[2] - v0[2]},
-                            {v2[0] - v1[0], v2[1] - v1[1], v2[2] - v1[2]},
-                            {v0[0] - v2[0], v0[1] - v2[1], v0[2] - v2[2]}};
     // nine edge cross axes: axis = e_box(a) x e(i)
     for (int i = 0; i < 3; i++) {
         for (int a = 0; a < 3; a++) {
             double ax[3] = {0, 0, 0};
             const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
-            ax[b1] = -e[i][b2];
-            ax[b2] = e[i][b1];
+            ax[b1] = -T.e[i][b2];
+            ax[b2] = T.e[i][b1];
             const double p0 = ax[0] * v0[0] + ax[1] * v0[1] + ax[2] * v0[2];
             const double p1 = ax[0] * v1[0] + ax[1] * v1[1] + ax[2] * v1[2];
             const double p2 = ax[0] * v2[0] + ax[1] * v2[1] + ax[2] * v2[2];
@@ -420,12 +455,6 @@ __device__ bool tri_box_overlap(const double* c, double hs, const double v0in[3]
             if (axis_sep(p0, p1, p2, r * (1.0 + 1e-9))) return false;
         }
     }
-    // triangle plane
-    const double n[3] = {e[0][1] * e[1][2] - e[0][2] * e[1][1], e[0][2] * e[1][0] - e[0][0] * e[1][2],
-                         e[0][0] * e[1][1] - e[0][1] * e[1][0]};
-    const double dist = n[0] * v0[0] + n[1] * v0[1] + n[2] * v0[2];
-    const double r = hs * (fabs(n[0]) + fabs(n[1]) + fabs(n[2]));
-    if (fabs(dist) > r * (1.0 + 1e-9) + 1e-12 * (fabs(n[0]) + fabs(n[1]) + fabs(n[2]))) return false;
     return true;
 }
 
@@ -439,7 +468,8 @@ __global__ void __launch_bounds__(64) k_links_pass1(DevMesh m, DevLevel d, int32
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m.nt; base += stride) {
         const int64_t t = base + threadIdx.x;
-        double v[3][3];
+        SatTri T;
+        double (&v)[3][3] = T.v;
         int lo[3] = {0, 0, 0}, hi[3] = {-1, -1, -1};
         bool live = t < m.nt;
         if (live) {
@@ -447,6 +477,7 @@ __global__ void __launch_bounds__(64) k_links_pass1(DevMesh m, DevLevel d, int32
                 const int vid = m.tris[3 * t + i];
                 for (int a = 0; a < 3; a++) v[i][a] = load_coord(m, vid, a);
             }
+            sat_setup(T);
             // zero-area triangles never meet a segment: exact test (all three
             // coordinate-plane projections have zero area)
             if (orient2d_filter<double>(v[0][1], v[0][2], v[1][1], v[1][2], v[2][1], v[2][2], 0.0) == 0 &&
@@ -475,14 +506,13 @@ __global__ void __launch_bounds__(64) k_links_pass1(DevMesh m, DevLevel d, int32
             int key = 0;
             if (it < n) {
                 const int bx = lo[0] + it % sx, by = lo[1] + (it / sx) % sy, bz = lo[2] + it / (sx * sy);
-                const int idx = forest_lookup(d, bx, by, bz);
-                if (idx >= 0) {
-                    // box [4bh - h/2, 4(b+1)h + h/2] reached by the block's links,
-                    // plus a relative margin
-                    const double c[3] = {(bx + 0.5) * bw, (by + 0.5) * bw, (bz + 0.5) * bw};
-                    const double hs = (0.5 * bw + 0.5 * h) * (1.0 + 1e-9);
-                    has = tri_box_overlap(c, hs, v[0], v[1], v[2]);
-                    key = idx;
+                // box [4bh - h/2, 4(b+1)h + h/2] reached by the block's links,
+                // plus a relative margin; the block is looked up only on overlap
+                const double c[3] = {(bx + 0.5) * bw, (by + 0.5) * bw, (bz + 0.5) * bw};
+                const double hs = (0.5 * bw + 0.5 * h) * (1.0 + 1e-9);
+                if (tri_box_overlap(c, hs, T)) {
+                    key = forest_lookup(d, bx, by, bz);
+                    has = key >= 0;
                 }
             }
             app.add(has, key, (int32_t)t);

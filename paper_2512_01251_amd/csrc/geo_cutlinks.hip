@@ -410,7 +410,7 @@ __device__ __forceinline__ int fast_test(const Cand<R>& C, const R X[3], const R
     return 1;
 }
 
-constexpr int CL_MAXC = 8;  // box-passing candidates kept per link and pass
+constexpr int CL_MAXC = 16;  // box-passing candidates taken per link and round
 
 // packed nearest-hit key: t in [0,1] as 37-bit fixed point, then the
 // triangle id (27 bits); the minimum key is the nearest hit, ties (equal t to
@@ -485,11 +485,14 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
                                              unsigned long long* keys, int32_t* mark, int32_t* fixq,
                                              int32_t* fixn, uint64_t* stats) {
     __shared__ Cand<R> cand[CL_CAND];
-    __shared__ CBox cbox[CL_CAND];
+    // box test as bit masks over the staged candidates: for axis a and lattice
+    // position j in -1..4, bmask[12a + 1 + j] holds the candidates with
+    // hi_a >= j and bmask[12a + 7 + j] those with lo_a <= j
+    __shared__ unsigned long long bmask[36];
+    __shared__ uint8_t cflag[CL_CAND];
     __shared__ uint32_t smask[64];
     __shared__ int spre[65];
     __shared__ unsigned halo[36];
-    __shared__ uint8_t plist[64 * CL_MAXC];   // per link: box-passing candidate slots
     __shared__ uint16_t flat[64 * CL_MAXC];   // flattened pairs: owner lane | candidate slot << 6
     __shared__ unsigned long long lbest[64];  // nearest hit of each lane's link (packed key)
     __shared__ int sk[64];                    // link (t, k) of each lane, packed t | k << 8
@@ -505,6 +508,8 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
     if (t0 >= t1) return;
     int64_t b = task_block(task_off, d.nblocks, t0);
     int64_t b_prev = -1;
+    int64_t staged_b = -1;  // (block, candidate chunk) held in LDS
+    int staged_c = -1;
     for (int task = t0; task < t1; task++) {
         while (task >= task_off[b + 1]) b++;  // uniform
         const int n = blk_off[b + 1] - blk_off[b];
@@ -512,9 +517,11 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
         if (c1 > lcap) c1 = lcap;
         if (c0 > c1) c0 = c1;
         const int nc = (int)(c1 - c0);
-        const int ncc = nc > 0 ? (nc + CL_CAND - 1) / CL_CAND : 1;
+        // a block's tasks run candidate chunk by candidate chunk, so that
+        // consecutive link chunks reuse the staged candidates
+        const int nlc = (n + 63) / 64;
         const int local = task - task_off[b];
-        const int lchunk = local / ncc, cchunk = local % ncc;
+        const int cchunk = local / nlc, lchunk = local % nlc;
         const int b0[3] = {4 * d.bcoord[3 * b], 4 * d.bcoord[3 * b + 1], 4 * d.bcoord[3 * b + 2]};
         st.tasks++;
         if (b != b_prev) {  // uniform
@@ -532,10 +539,30 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
         }
         const int cb = cchunk * CL_CAND;
         const int nstage = nc - cb < CL_CAND ? (nc - cb > 0 ? nc - cb : 0) : CL_CAND;
-        __syncthreads();
-        if (lane < nstage) {
-            stage_cand<R>(m, L, lval[c0 + cb + lane], b0, cand[lane], cbox[lane]);
-            st.staged++;
+        if (b != staged_b || cchunk != staged_c) {  // uniform
+            staged_b = b;
+            staged_c = cchunk;
+            __syncthreads();
+            float blo[3] = {1e30f, 1e30f, 1e30f}, bhi[3] = {-1e30f, -1e30f, -1e30f};
+            if (lane < nstage) {
+                CBox bx;
+                stage_cand<R>(m, L, lval[c0 + cb + lane], b0, cand[lane], bx);
+                cflag[lane] = (uint8_t)bx.lo.w;
+                blo[0] = bx.lo.x; blo[1] = bx.lo.y; blo[2] = bx.lo.z;
+                bhi[0] = bx.hi.x; bhi[1] = bx.hi.y; bhi[2] = bx.hi.z;
+                st.staged++;
+            }
+            unsigned long long mine = 0;
+#pragma unroll
+            for (int a = 0; a < 3; a++)
+#pragma unroll
+                for (int j = 0; j < 6; j++) {
+                    const unsigned long long A = __ballot(bhi[a] >= (float)(j - 1));
+                    const unsigned long long B = __ballot(blo[a] <= (float)(j - 1));
+                    if (lane == 12 * a + j) mine = A;
+                    if (lane == 12 * a + 6 + j) mine = B;
+                }
+            if (lane < 36) bmask[lane] = mine;
         }
         __syncthreads();
         const int li = lchunk * 64 + lane;
@@ -557,24 +584,22 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
         sk[lane] = t | (k << 8);
         int cx, cy, cz;
         dirvec(k, cx, cy, cz);
-        const float slo[3] = {(float)geo_min(t & 3, (t & 3) + cx), (float)geo_min((t >> 2) & 3, ((t >> 2) & 3) + cy),
-                              (float)geo_min(t >> 4, (t >> 4) + cz)};
-        const float shi[3] = {(float)geo_max(t & 3, (t & 3) + cx), (float)geo_max((t >> 2) & 3, ((t >> 2) & 3) + cy),
-                              (float)geo_max(t >> 4, (t >> 4) + cz)};
+        const int slo[3] = {geo_min(t & 3, (t & 3) + cx), geo_min((t >> 2) & 3, ((t >> 2) & 3) + cy),
+                            geo_min(t >> 4, (t >> 4) + cz)};
+        const int shi[3] = {geo_max(t & 3, (t & 3) + cx), geo_max((t >> 2) & 3, ((t >> 2) & 3) + cy),
+                            geo_max(t >> 4, (t >> 4) + cz)};
         const int64_t lbase = (int64_t)blk_off[b] + lchunk * 64;
         lbest[lane] = KEY_MISS;
-        int ci = 0;
-        while (ci < nstage) {  // uniform
-            // phase 1: box tests, each lane lists its passing candidates
-            int cnt = 0;
-            for (; ci < nstage; ci++) {
-                const float4 lo4 = cbox[ci].lo, hi4 = cbox[ci].hi;
-                const bool pass = active && !(hi4.x < slo[0] || lo4.x > shi[0] || hi4.y < slo[1] ||
-                                              lo4.y > shi[1] || hi4.z < slo[2] || lo4.z > shi[2]);
-                if (pass) plist[lane * CL_MAXC + cnt++] = (uint8_t)ci;
-                if (__any(cnt == CL_MAXC)) { ci++; break; }
-            }
-            // flatten the (link, candidate) pairs over the wave
+        // phase 1: candidates whose box meets the link's segment box
+        unsigned long long pm = 0;
+        if (active) {
+            pm = bmask[1 + slo[0]] & bmask[7 + shi[0]] & bmask[13 + slo[1]] & bmask[19 + shi[1]] &
+                 bmask[25 + slo[2]] & bmask[31 + shi[2]];
+        }
+        while (__any(pm != 0)) {  // uniform
+            // flatten up to CL_MAXC pairs per link over the wave
+            const int pc = __popcll(pm);
+            const int cnt = pc < CL_MAXC ? pc : CL_MAXC;
             int inc2 = cnt;
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
@@ -582,7 +607,11 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
                 if (lane >= o) inc2 += tt;
             }
             const int pbase = inc2 - cnt;
-            for (int j = 0; j < cnt; j++) flat[pbase + j] = (uint16_t)(lane | (plist[lane * CL_MAXC + j] << 6));
+            for (int j = 0; j < cnt; j++) {
+                const int slot = __ffsll(pm) - 1;
+                pm &= pm - 1;
+                flat[pbase + j] = (uint16_t)(lane | (slot << 6));
+            }
             const int P = __shfl(inc2, 63, 64);
             __syncthreads();
             st.pairs += cnt;
@@ -599,7 +628,7 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
                 const R X[3] = {(R)Xi[0], (R)Xi[1], (R)Xi[2]};
                 const R Y[3] = {(R)(Xi[0] + ox), (R)(Xi[1] + oy), (R)(Xi[2] + oz)};
                 const Cand<R>& C = cand[cidx];
-                const int flags = (int)cbox[cidx].lo.w;
+                const int flags = cflag[cidx];
                 R tr = 0, terr = 0;
                 const int res = (flags & C_SLOW) ? -1 : fast_test<R>(C, X, Y, tr, terr);
                 unsigned long long kk = KEY_MISS;
