@@ -190,8 +190,13 @@ int geo_refine_flags(const geo_level* lv, const uint64_t* solid, int32_t n_prop,
  *   the table lists every set bit in the order (block, t, k):
  *     link_cell = b*64 + t, link_dir = k,
  *     link_q = min t in (0,1] with x + t h c_k on the surface,
- *     link_tri = a triangle attaining it (the smallest index at exact ties);
- *   *d_nlinks (device int64) = number of links; entries >= cap not written.
+ *     link_tri = a triangle attaining it: the smallest index among the
+ *       triangles whose hit parameters round to the same multiple of
+ *       1/(2^37 - 1) (exact ties included); at most 2^27 triangles;
+ *   *d_nlinks (device int64) = number of links, exact; entries >= cap are not
+ *     written.  The table's offsets are int32: with more than 2^31 - 1 links
+ *     the outputs are unspecified (accesses stay in bounds) and the caller
+ *     must split the level.
  * rows: ROWS bins of level L; links: LINKS bins of level L.
  */
 int geo_cutlinks(const geo_mesh* mesh, const geo_level* lv, const geo_bins* rows,

@@ -49,18 +49,27 @@ __device__ __forceinline__ unsigned halo_bits(const int32_t* off, const int32_t*
                                               int xm1, int nx) {
     int64_t e0 = off[line], e1 = off[line + 1];
     if (e1 > cap) e1 = cap;
+    if (e0 < 0) e0 = 0;
     unsigned par = 0, surf = 0;
-    for (int64_t e = e0; e < e1; e++) {
-        const int32_t v = val[e];
-        if (v >= 0) {
-            int n = v - xm1;
-            n = n < 0 ? 0 : (n > 6 ? 6 : n);
-            par ^= (1u << n) - 1u;
-        } else {
-            int a = (v & 0x7fff) - xm1, b = ((v >> 15) & 0x7fff) - xm1;
-            a = a < 0 ? 0 : a;
-            b = b > 5 ? 5 : b;
-            if (a <= b) surf |= ((1u << (b + 1)) - 1u) & ~((1u << a) - 1u);
+    for (int64_t e = e0; e < e1; e += 4) {
+        // four independent loads in flight before the first use
+        int32_t v4[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) v4[i] = e + i < e1 ? val[e + i] : 0;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            if (e + i >= e1) break;
+            const int32_t v = v4[i];
+            if (v >= 0) {
+                int n = v - xm1;
+                n = n < 0 ? 0 : (n > 6 ? 6 : n);
+                par ^= (1u << n) - 1u;
+            } else {
+                int a = (v & 0x7fff) - xm1, b = ((v >> 15) & 0x7fff) - xm1;
+                a = a < 0 ? 0 : a;
+                b = b > 5 ? 5 : b;
+                if (a <= b) surf |= ((1u << (b + 1)) - 1u) & ~((1u << a) - 1u);
+            }
         }
     }
     unsigned r = (par | surf) & 0x3fu;
@@ -122,10 +131,6 @@ __global__ void __launch_bounds__(64) k_cl_mask(DevLevel d, const int32_t* off, 
     }
 }
 
-__global__ void k_cl_total(const int32_t* blk_off, int64_t nb, int64_t* d_nlinks) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *d_nlinks = blk_off[nb];
-}
-
 // ------------------------------------------------------------------------
 // candidate records
 // ------------------------------------------------------------------------
@@ -166,14 +171,15 @@ __device__ __forceinline__ float up_f(double x) {
 // Stage one candidate: local float64 coordinates (exact unless flagged slow),
 // certified plane coefficients in R, float64 plane, float box.
 template <typename R>
-__device__ void stage_cand(const DevMesh& m, int L, int tri, const int b0[3], Cand<R>& C, CBox& B) {
+__device__ void stage_cand(const DevMesh& m, int L, int tri, const int vid[3], const int b0[3], Cand<R>& C,
+                           CBox& B) {
     const double s = ldexp(1.0, L);
     double v[3][3];
     bool exact = true;
 #pragma unroll
     for (int i = 0; i < 3; i++) {
         double g[3];
-        vert_scaled(m, m.tris[3 * (int64_t)tri + i], s, g);
+        vert_scaled(m, vid[i], s, g);
 #pragma unroll
         for (int a = 0; a < 3; a++) {
             const double o = (double)b0[a];
@@ -428,6 +434,7 @@ __global__ void k_cl_ntask(int64_t nb, const int32_t* blk_off, const int32_t* lo
         const int n = blk_off[b + 1] - blk_off[b];
         int64_t c0 = loff[b], c1 = loff[b + 1];
         if (c1 > lcap) c1 = lcap;
+        if (c0 < 0) c0 = 0;
         const int nc = c1 > c0 ? (int)(c1 - c0) : 0;
         ntask[b] = n > 0 ? ((n + 63) / 64) * (nc > 0 ? (nc + CL_CAND - 1) / CL_CAND : 1) : 0;
     }
@@ -477,6 +484,20 @@ __device__ __forceinline__ int64_t task_block(const int32_t* task_off, int64_t n
     return lo;
 }
 
+// block of `task` searching forward from block b (task_off[b] <= task): the
+// wave tests 64 blocks per step, so runs of blocks without tasks cost one
+// load each 64 blocks
+__device__ __forceinline__ int64_t advance_block(const int32_t* task_off, int64_t nb, int64_t b, int task) {
+    const int lane = threadIdx.x;
+    for (;;) {
+        const int64_t i = b + 1 + lane;  // block b + lane ends at task_off[i]
+        const bool ends_after = i > nb || task < task_off[i];
+        const unsigned long long m = __ballot(ends_after);
+        if (m) return b + (__ffsll(m) - 1);
+        b += 64;
+    }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_t* roff, const int32_t* rval,
                                              int64_t rcap, const int32_t* loff, const int32_t* lval, int64_t lcap,
@@ -510,11 +531,17 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
     int64_t b_prev = -1;
     int64_t staged_b = -1;  // (block, candidate chunk) held in LDS
     int staged_c = -1;
+    // prefetch of the next staging unit: candidate triangle (at staging) and
+    // its vertex ids (at the end of the task), so staging waits for one load
+    int pf_task = -1, pf_n = 0;  // first task and candidate count of the prefetched unit
+    bool pf_vid_ok = false;
+    int pf_tri = 0, pf_v0 = 0, pf_v1 = 0, pf_v2 = 0;
     for (int task = t0; task < t1; task++) {
-        while (task >= task_off[b + 1]) b++;  // uniform
+        if (task >= task_off[b + 1]) b = advance_block(task_off, d.nblocks, b + 1, task);  // uniform
         const int n = blk_off[b + 1] - blk_off[b];
         int64_t c0 = loff[b], c1 = loff[b + 1];
         if (c1 > lcap) c1 = lcap;
+        if (c0 < 0) c0 = 0;
         if (c0 > c1) c0 = c1;
         const int nc = (int)(c1 - c0);
         // a block's tasks run candidate chunk by candidate chunk, so that
@@ -544,13 +571,42 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
             staged_c = cchunk;
             __syncthreads();
             float blo[3] = {1e30f, 1e30f, 1e30f}, bhi[3] = {-1e30f, -1e30f, -1e30f};
-            if (lane < nstage) {
+            const bool from_pf = pf_task == task;  // uniform
+            const int tri = lane < nstage ? (from_pf ? pf_tri : lval[c0 + cb + lane]) : -1;
+            // entries of an overflowed bin are not triangle ids: left inert
+            if (lane < nstage && (unsigned)tri < (unsigned)m.nt) {
+                int vid[3];
+                if (from_pf && pf_vid_ok) {
+                    vid[0] = pf_v0;
+                    vid[1] = pf_v1;
+                    vid[2] = pf_v2;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 3; i++) vid[i] = m.tris[3 * (int64_t)tri + i];
+                }
                 CBox bx;
-                stage_cand<R>(m, L, lval[c0 + cb + lane], b0, cand[lane], bx);
+                stage_cand<R>(m, L, tri, vid, b0, cand[lane], bx);
                 cflag[lane] = (uint8_t)bx.lo.w;
                 blo[0] = bx.lo.x; blo[1] = bx.lo.y; blo[2] = bx.lo.z;
                 bhi[0] = bx.hi.x; bhi[1] = bx.hi.y; bhi[2] = bx.hi.z;
                 st.staged++;
+            }
+            // first task of the next staging unit, and its candidates
+            pf_task = -1;
+            pf_vid_ok = false;
+            const int tn = task_off[b] + (cchunk + 1) * nlc;
+            if (tn < t1) {
+                const int64_t bn = tn < task_off[b + 1] ? b : advance_block(task_off, d.nblocks, b + 1, tn);
+                const int nn = blk_off[bn + 1] - blk_off[bn];
+                int64_t d0 = loff[bn], d1 = loff[bn + 1];
+                if (d1 > lcap) d1 = lcap;
+                if (d0 < 0) d0 = 0;
+                if (d0 > d1) d0 = d1;
+                const int cbn = ((tn - task_off[bn]) / ((nn + 63) / 64)) * CL_CAND;
+                const int rem = (int)(d1 - d0) - cbn;
+                pf_n = rem < CL_CAND ? (rem > 0 ? rem : 0) : CL_CAND;
+                if (lane < pf_n) pf_tri = lval[d0 + cbn + lane];
+                pf_task = tn;
             }
             unsigned long long mine = 0;
 #pragma unroll
@@ -641,7 +697,7 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
                     // not certain: the link is redone exactly by the deferred pass
                     st.fb++;
                     const int64_t pos = lbase + ow;
-                    if (pos < cap && atomicExch(&mark[pos], 1) == 0) {
+                    if (pos >= 0 && pos < cap && atomicExch(&mark[pos], 1) == 0) {
                         const int qi = atomicAdd(fixn, 1);
                         if (qi < cap) fixq[qi] = (int32_t)pos;
                     }
@@ -653,13 +709,21 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
         const unsigned long long best = lbest[lane];
         if (active) {
             const int64_t pos = lbase + lane;
-            if (pos < cap) {
+            if (pos >= 0 && pos < cap) {
                 if (cchunk == 0) {
                     link_cell[pos] = (int32_t)(64 * b + t);
                     link_dir[pos] = (uint8_t)k;
                 }
                 if (best != KEY_MISS) atomicMin(&keys[pos], best);
             }
+        }
+        if (pf_task >= 0 && !pf_vid_ok) {  // uniform
+            if (lane < pf_n && (unsigned)pf_tri < (unsigned)m.nt) {
+                pf_v0 = m.tris[3 * (int64_t)pf_tri];
+                pf_v1 = m.tris[3 * (int64_t)pf_tri + 1];
+                pf_v2 = m.tris[3 * (int64_t)pf_tri + 2];
+            }
+            pf_vid_ok = true;
         }
     }
     if (stats) {
@@ -693,9 +757,11 @@ __global__ void __launch_bounds__(64) k_cl_fix(DevMesh m, DevLevel d, const int3
         const double Y[3] = {X[0] + cx, X[1] + cy, X[2] + cz};
         int64_t c0 = loff[b], c1 = loff[b + 1];
         if (c1 > lcap) c1 = lcap;
+        if (c0 < 0) c0 = 0;
         unsigned long long best = KEY_MISS;
         for (int64_t c = c0 + threadIdx.x; c < c1; c += 64) {
             const int tri = lval[c];
+            if ((unsigned)tri >= (unsigned)m.nt) continue;  // entry of an overflowed bin
             double A[3], B[3], Cc[3];
             vert_scaled(m, m.tris[3 * (int64_t)tri], s, A);
             vert_scaled(m, m.tris[3 * (int64_t)tri + 1], s, B);
@@ -760,9 +826,10 @@ int launch_cutlinks(const DevMesh& m, const DevLevel& d, const geo_bins* rows, c
     const unsigned g = (unsigned)(nb < 262144 ? nb : 262144);
     k_cl_mask<<<g, 64, 0, s>>>(d, rows->off, rows->val, rows->cap, links->off, lattice, link_mask, blk_cnt);
     GEO_LAUNCH_CHECK();
-    int rc = geo_scan_exclusive(blk_cnt, blk_off, nb, partials, s);
+    // exact link count (the table's offsets are int32)
+    int rc = geo_sum_i32(blk_cnt, nb, d_nlinks, s);
     if (rc != GEO_OK) return rc;
-    k_cl_total<<<1, 64, 0, s>>>(blk_off, nb, d_nlinks);
+    if ((rc = geo_scan_exclusive(blk_cnt, blk_off, nb, partials, s)) != GEO_OK) return rc;
     const unsigned gb = (unsigned)((nb + 255) / 256 < 65536 ? (nb + 255) / 256 : 65536);
     k_cl_ntask<<<gb, 256, 0, s>>>(nb, blk_off, links->off, links->cap, ntask);
     GEO_LAUNCH_CHECK();

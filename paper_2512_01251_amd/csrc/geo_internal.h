@@ -264,6 +264,7 @@ int geo_scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* part
 size_t geo_scan_partials_bytes(int64_t n);
 int geo_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 int geo_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
+int geo_sum_i32(const int32_t* in, int64_t n, int64_t* out, hipStream_t s);
 
 int launch_rows_pass1(const DevMesh& m, const DevLevel& d, int precision, int32_t* cnt,
                       int2* pairs, int64_t cap, int64_t* d_count, uint64_t* d_stats, hipStream_t s);

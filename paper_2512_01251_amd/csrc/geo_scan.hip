@@ -107,6 +107,22 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t v, int64_t n) {
         p[i] = v;
 }
 
+// *out += sum of in[0..n-1] in 64-bit (one atomic per workgroup of 256)
+__global__ void __launch_bounds__(256) k_sum_i32(const int32_t* in, int64_t n, unsigned long long* out) {
+    __shared__ unsigned long long part[4];
+    unsigned long long acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc += (unsigned long long)(uint32_t)in[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t = part[0] + part[1] + part[2] + part[3];
+        if (t) atomicAdd(out, t);
+    }
+}
+
 inline unsigned grid_for(int64_t n, int threads) {
     int64_t g = (n + threads - 1) / threads;
     if (g > 65536) g = 65536;
@@ -147,6 +163,17 @@ int geo_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
 int geo_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s) {
     if (n <= 0) return GEO_OK;
     k_fill_u64<<<grid_for(n, 256), 256, 0, s>>>(p, v, n);
+    GEO_LAUNCH_CHECK();
+    return GEO_OK;
+}
+
+// *out = sum of the non-negative in[0..n-1], exact in 64 bits
+int geo_sum_i32(const int32_t* in, int64_t n, int64_t* out, hipStream_t s) {
+    int rc = geo_fill_u64(reinterpret_cast<uint64_t*>(out), 0, 1, s);
+    if (rc != GEO_OK || n <= 0) return rc;
+    int64_t g = (n + 255) / 256;
+    if (g > 256) g = 256;
+    k_sum_i32<<<(unsigned)g, 256, 0, s>>>(in, n, reinterpret_cast<unsigned long long*>(out));
     GEO_LAUNCH_CHECK();
     return GEO_OK;
 }

@@ -30,20 +30,29 @@ __device__ __forceinline__ unsigned line_nibble(const int32_t* off, const int32_
                                                 int64_t line, int x0) {
     int64_t e0 = off[line], e1 = off[line + 1];
     if (e1 > cap) e1 = cap;
+    if (e0 < 0) e0 = 0;
     unsigned par = 0, surf = 0;
-    for (int64_t e = e0; e < e1; e++) {
-        const int32_t v = val[e];
-        if (v >= 0) {
-            // cells x < v see this crossing ahead: flip those of x0..x0+3
-            int n = v - x0;
-            n = n < 0 ? 0 : (n > 4 ? 4 : n);
-            par ^= (1u << n) - 1u;
-        } else {
-            const int lo = v & 0x7fff, hi = (v >> 15) & 0x7fff;
-            int a = lo - x0, b = hi - x0;
-            a = a < 0 ? 0 : a;
-            b = b > 3 ? 3 : b;
-            if (a <= b) surf |= ((1u << (b + 1)) - 1u) & ~((1u << a) - 1u);
+    for (int64_t e = e0; e < e1; e += 4) {
+        // four independent loads in flight before the first use
+        int32_t v4[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) v4[i] = e + i < e1 ? val[e + i] : 0;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            if (e + i >= e1) break;
+            const int32_t v = v4[i];
+            if (v >= 0) {
+                // cells x < v see this crossing ahead: flip those of x0..x0+3
+                int n = v - x0;
+                n = n < 0 ? 0 : (n > 4 ? 4 : n);
+                par ^= (1u << n) - 1u;
+            } else {
+                const int lo = v & 0x7fff, hi = (v >> 15) & 0x7fff;
+                int a = lo - x0, b = hi - x0;
+                a = a < 0 ? 0 : a;
+                b = b > 3 ? 3 : b;
+                if (a <= b) surf |= ((1u << (b + 1)) - 1u) & ~((1u << a) - 1u);
+            }
         }
     }
     return (par | surf) & 0xfu;

@@ -3,9 +3,10 @@
 For L = 0 .. L_f: ROWS bins and solid voxelization of level L; for L < L_f
 the refinement flags produce the blocks of level L+1 (Methodology, overview:
 voxelization and refinement run level by level, top-down).  On L_f the LINKS
-bins and the cut-link table follow.  The host only sizes buffers: it reads
-back the next level's block count and the bin / link counts (a buffer that
-was too small is grown and the call repeated).
+bins and the cut-link table follow.  The host only sizes buffers: it waits for
+the next level's block count after each refinement, and for all bin and link
+counts once at the end (a pass that overflowed a buffer is redone with larger
+buffers; every kernel clamps to the capacity it is given).
 """
 from __future__ import annotations
 
@@ -64,7 +65,7 @@ class Embedder:
     def __init__(self, device="cuda"):
         self.device = torch.device(device)
         self.ws = torch.empty(0, dtype=torch.uint8, device=self.device)
-        self.caps: dict = {}
+        self.caps: dict = {}                 # remembered buffer capacities
         self.events = None   # list of (name, start_event, end_event) when timing
 
     # -- helpers ---------------------------------------------------------------
@@ -82,24 +83,44 @@ class Embedder:
     def embed(self, verts: torch.Tensor, tris: torch.Tensor, n0, lf: int, lattice: int,
               d_spec: float = 2.0, precision: str = "f32", with_links: bool = True,
               with_mask: bool = False) -> Embedding:
+        # each pass sizes at least the first level whose buffers overflowed
+        for _ in range(lf + 4):
+            out = self._embed_once(verts, tris, n0, lf, lattice, d_spec, precision, with_links, with_mask)
+            if out is not None:
+                return out
+        raise RuntimeError("buffer capacities did not converge")
+
+    def _embed_once(self, verts, tris, n0, lf, lattice, d_spec, precision, with_links, with_mask):
+        """One pass over all levels.  Bin and link counts are checked once, at
+        the end: every kernel clamps to the capacity it is given, so a pass that
+        overflowed a buffer is memory-safe and is simply redone with larger
+        buffers (None is returned).  The host waits only for the child count of
+        each level (it sizes the next level) and for the final counts."""
         dev = self.device
         prec = PRECISIONS[precision]
         mesh = make_mesh(verts, tris)
         n_prop = geo_nprop(d_spec)
-        stats = torch.zeros(GEO_NSTATS, dtype=torch.int64, device=dev)
+        # one zero-filled buffer for the statistics and every device counter
+        ctr = torch.zeros(GEO_NSTATS + 2 * lf + 4, dtype=torch.int64, device=dev)
+        stats = ctr[:GEO_NSTATS]
+        cnt = lambda i: ctr[GEO_NSTATS + i:GEO_NSTATS + i + 1]
+        checks = []   # (counter index, capacity, capacity key, apply(count))
         nb0 = (n0[0] // 4) * (n0[1] // 4) * (n0[2] // 4)
         bcoord = torch.empty((nb0, 3), dtype=torch.int32, device=dev)
         geo_level0_blocks(n0, bcoord)
         out = Embedding(tuple(n0), lf, lattice)
         child_maps = []
+        rows = None
         for L in range(lf + 1):
             lvd = make_level(n0, L, bcoord, child_maps)
             rec = Level(L, bcoord)
             nkeys = (n0[1] << L) * (n0[2] << L)
-            rec.rows_off, rec.rows_val = self._bins(mesh, lvd, GEO_BINS_ROWS, prec, nkeys, stats,
-                                                    ("rows", L), max(4096, 2 * mesh.nt), f"rows{L}")
-            rows = make_bins(GEO_BINS_ROWS, nkeys, rec.rows_off, rec.rows_val, rec.rows_val.numel(),
-                             self._count)
+            key = ("rows", L)
+            cap = self.caps.get(key, max(4096, 2 * mesh.nt))
+            rec.rows_off, val = self._bins(mesh, lvd, GEO_BINS_ROWS, prec, nkeys, stats, cap, cnt(L), f"rows{L}")
+            checks.append((L, cap, key, lambda c, rec=rec, val=val: setattr(rec, "rows_val", val[:c])))
+            rows = make_bins(GEO_BINS_ROWS, nkeys, rec.rows_off, val, cap, cnt(L))
+            rec.rows_val = val
             rec.solid = torch.empty(lvd.nblocks, dtype=torch.int64, device=dev)
             with self._timed(f"voxelize{L}"):
                 geo_voxelize(lvd, rows, rec.solid)
@@ -109,7 +130,7 @@ class Embedder:
                 rec.refine = torch.empty(nb, dtype=torch.uint8, device=dev)
                 rec.child_map = torch.empty(nb, dtype=torch.int32, device=dev)
                 child = torch.empty((8 * nb, 3), dtype=torch.int32, device=dev)
-                d_n = torch.zeros(1, dtype=torch.int64, device=dev)
+                d_n = cnt(lf + 1 + L)
                 ws = self._workspace(geo_workspace_size(GEO_CALL_REFINE, nb, 0))
                 with self._timed(f"refine{L}"):
                     geo_refine_flags(lvd, rec.solid, n_prop, rec.bclass, rec.refine, rec.child_map, child,
@@ -117,59 +138,65 @@ class Embedder:
                 nchild = int(d_n.item())
                 child_maps.append(rec.child_map)
                 bcoord = child[:nchild]
-            else:
-                self._rows_last = rows
             out.levels.append(rec)
         if with_links:
-            out.links = self._cutlinks(mesh, n0, lf, out.levels[-1], child_maps, lattice, prec, stats, with_mask)
+            out.links = self._cutlinks(mesh, n0, lf, out.levels[-1], child_maps, rows, lattice, prec, stats,
+                                       with_mask, cnt(2 * lf + 1), cnt(2 * lf + 2), checks)
+        # the final wait: every count at once
+        counts = ctr[GEO_NSTATS:].cpu().tolist()
+        if with_links and counts[2 * lf + 2] > 2 ** 31 - 1:
+            raise RuntimeError(f"{counts[2 * lf + 2]} links exceed the table's int32 offsets")
+        ok = True
+        for i, cap, key, apply in checks:
+            if counts[i] > cap:
+                self.caps[key] = int(counts[i] * 1.1) + 1024
+                ok = False
+            else:
+                self.caps[key] = cap
+        if not ok:
+            return None
+        for i, cap, key, apply in checks:
+            apply(counts[i])
         out.stats = stats
         return out
 
-    def _bins(self, mesh, lvd, kind, prec, nkeys, stats, key, cap0, tname):
+    def _bins(self, mesh, lvd, kind, prec, nkeys, stats, cap, d_count, tname):
         dev = self.device
         off = torch.empty(nkeys + 1, dtype=torch.int32, device=dev)
-        cap = self.caps.get(key, cap0)
-        self._count = torch.zeros(1, dtype=torch.int64, device=dev)
+        val = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        bins = make_bins(kind, nkeys, off, val, cap, d_count)
         call = GEO_CALL_BINS_ROWS if kind == GEO_BINS_ROWS else GEO_CALL_BINS_LINKS
-        for _ in range(3):
-            val = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
-            bins = make_bins(kind, nkeys, off, val, cap, self._count)
-            ws = self._workspace(geo_workspace_size(call, nkeys, cap))
-            with self._timed(tname):
-                geo_build_bins(mesh, lvd, kind, prec, bins, stats, ws)
-            need = int(self._count.item())
-            if need <= cap:
-                self.caps[key] = cap
-                return off, val[:need]
-            cap = int(need * 1.1) + 1024
-        raise RuntimeError("bins capacity did not converge")
+        ws = self._workspace(geo_workspace_size(call, nkeys, cap))
+        with self._timed(tname):
+            geo_build_bins(mesh, lvd, kind, prec, bins, stats, ws)
+        return off, val
 
-    def _cutlinks(self, mesh, n0, lf, rec, child_maps, lattice, prec, stats, with_mask):
+    def _cutlinks(self, mesh, n0, lf, rec, child_maps, rows, lattice, prec, stats, with_mask, d_bins, d_n,
+                  checks):
         dev = self.device
         lvd = make_level(n0, lf, rec.bcoord, child_maps)
         nb = lvd.nblocks
-        loff, lval = self._bins(mesh, lvd, GEO_BINS_LINKS, prec, nb, stats, ("links", lf),
-                                max(4096, 8 * mesh.nt), "linkbins")
-        links = make_bins(GEO_BINS_LINKS, nb, loff, lval, lval.numel(), self._count)
-        rows = make_bins(GEO_BINS_ROWS, (n0[1] << lf) * (n0[2] << lf), rec.rows_off, rec.rows_val,
-                         rec.rows_val.numel(), self._count)
+        key = ("links", lf)
+        bcap = self.caps.get(key, max(4096, 8 * mesh.nt))
+        loff, lval = self._bins(mesh, lvd, GEO_BINS_LINKS, prec, nb, stats, bcap, d_bins, "linkbins")
+        links = make_bins(GEO_BINS_LINKS, nb, loff, lval, bcap, d_bins)
         mask = torch.empty(nb * 64, dtype=torch.int32, device=dev) if with_mask else None
-        d_n = torch.zeros(1, dtype=torch.int64, device=dev)
-        cap = self.caps.get(("links_table", lf), max(4096, 4 * nb))
-        for _ in range(3):
-            ws = self._workspace(geo_workspace_size(GEO_CALL_CUTLINKS, nb, cap))
-            cell = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
-            dr = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
-            q = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
-            tri = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
-            with self._timed("cutlinks"):
-                geo_cutlinks(mesh, lvd, rows, links, lattice, prec, mask, cap, d_n, cell, dr, q, tri, stats, ws)
-            n = int(d_n.item())
-            if n <= cap:
-                self.caps[("links_table", lf)] = cap
-                return Links(mask, cell[:n], dr[:n], q[:n], tri[:n], loff, lval)
-            cap = int(n * 1.1) + 1024
-        raise RuntimeError("link capacity did not converge")
+        lkey = ("links_table", lf)
+        cap = self.caps.get(lkey, max(4096, 4 * nb))
+        ws = self._workspace(geo_workspace_size(GEO_CALL_CUTLINKS, nb, cap))
+        cell = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        dr = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
+        q = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+        tri = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        with self._timed("cutlinks"):
+            geo_cutlinks(mesh, lvd, rows, links, lattice, prec, mask, cap, d_n, cell, dr, q, tri, stats, ws)
+        L = Links(mask, cell, dr, q, tri, loff, lval)
+        checks.append((2 * lf + 1, bcap, key, lambda c: setattr(L, "bins_val", lval[:c])))
+
+        def _apply(c):
+            L.cell, L.dir, L.q, L.tri = cell[:c], dr[:c], q[:c], tri[:c]
+        checks.append((2 * lf + 2, cap, lkey, _apply))
+        return L
 
 
 class _NoTimer:

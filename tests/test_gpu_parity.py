@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from synth import configs
-from gpu_helpers import compare, gpu_embed, say
+from gpu_helpers import compare, gpu_embed, say, to_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -55,3 +55,28 @@ def test_runs_are_byte_identical():
         assert np.array_equal(x.solid.cpu().numpy(), y.solid.cpu().numpy())
     for f in ("mask", "cell", "dir", "q", "tri"):
         assert np.array_equal(getattr(a.links, f).cpu().numpy(), getattr(b.links, f).cpu().numpy()), f
+
+
+def test_overflowed_buffers_are_redone():
+    """Capacities primed far too small: every bin and link buffer overflows on
+    the first pass (kernels clamp to the capacity they are given), the counts
+    are checked once at the end of the pass, and the pass is redone until the
+    buffers fit.  The result equals a normal run."""
+    from paper_2512_01251_amd import pipeline
+    w, _ = _ref("star_small")
+    say("[parity] overflow redo: star_small f32 with capacities of 1")
+    V, T = to_gpu(w.mesh)
+    ref = pipeline.Embedder().embed(V, T, w.n0, w.lf, w.lattice, w.d_spec, "f32", True, with_mask=True)
+    e = pipeline.Embedder()
+    for L in range(w.lf + 1):
+        e.caps[("rows", L)] = 1
+    e.caps[("links", w.lf)] = 1
+    e.caps[("links_table", w.lf)] = 1
+    got = e.embed(V, T, w.n0, w.lf, w.lattice, w.d_spec, "f32", True, with_mask=True)
+    assert e.caps[("rows", 0)] > 1 and e.caps[("links_table", w.lf)] > 1
+    for x, y in zip(ref.levels, got.levels):
+        assert np.array_equal(x.bcoord.cpu().numpy(), y.bcoord.cpu().numpy())
+        assert np.array_equal(x.solid.cpu().numpy(), y.solid.cpu().numpy())
+        assert np.array_equal(np.sort(x.rows_val.cpu().numpy()), np.sort(y.rows_val.cpu().numpy()))
+    for f in ("mask", "cell", "dir", "q", "tri"):
+        assert np.array_equal(getattr(ref.links, f).cpu().numpy(), getattr(got.links, f).cpu().numpy()), f

@@ -201,3 +201,12 @@ def test_kernel_timer_host_side(geo):
     import ctypes as C
     assert geo.lib().geo_kernel_timer_read(0, None, None) == geo.GEO_ERR_ARG
     assert geo.lib().geo_kernel_timer_read(7, C.byref(C.c_double()), C.byref(C.c_int64())) == geo.GEO_ERR_ARG
+
+
+def test_smoke_workload_and_its_oracle_reference_build():
+    # smoke() runs on a GPU; its inputs and reference are built on the host
+    import __graft_entry__ as ge
+    import oracle
+    w = ge.smoke_workload()
+    ref = oracle.embed(w.mesh, w.n0, w.lf, w.lattice, w.d_spec)
+    assert ref["links"]["n"] > 0 and len(ref["levels"]) == w.lf + 1
