@@ -254,7 +254,7 @@ def main():
                      "flop_per_launch": flop, "link_cand_pairs": p_link, "cell_cand_pairs": p_cell,
                      "traffic_source": traffic_src},
         "ms_per_step_ci95": ci32 * 1e3 if ci32 else None,
-        "cells": cells, "links": n_links,
+        "cells": cells, "links": n_links, "link_bin_entries": int(out.links.bins_val.numel()),
         "blocks_per_level": [int(lv.bcoord.shape[0]) for lv in out.levels],
         "mcells_per_s_voxelize": cells / (vox_only / 1e3) / 1e6 if vox_only else None,
         "mcells_per_s_rows_voxelize": cells / (vox / 1e3) / 1e6 if vox else None,

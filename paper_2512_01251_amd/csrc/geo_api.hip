@@ -12,7 +12,8 @@ namespace {
 inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t bins_ws_bytes(int64_t nkeys, int64_t cap) {
-    return al(sizeof(int2) * (size_t)(cap > 0 ? cap : 0)) + al(sizeof(int32_t) * ((size_t)nkeys + 1)) +
+    const size_t c = (size_t)(cap > 0 ? cap : 0);
+    return al(sizeof(int2) * c) + al(sizeof(int32_t) * c) + al(sizeof(int32_t) * ((size_t)nkeys + 1)) +
            al(geo_scan_partials_bytes(nkeys));
 }
 
@@ -101,6 +102,8 @@ int geo_build_bins(const geo_mesh* mesh, const geo_level* lv, int32_t kind, int3
     char* p = static_cast<char*>(ws);
     int2* pairs = reinterpret_cast<int2*>(p);
     p += al(sizeof(int2) * (size_t)out->cap);
+    int32_t* rank = reinterpret_cast<int32_t*>(p);
+    p += al(sizeof(int32_t) * (size_t)out->cap);
     int32_t* cnt = reinterpret_cast<int32_t*>(p);
     p += al(sizeof(int32_t) * ((size_t)nkeys + 1));
     int32_t* partials = reinterpret_cast<int32_t*>(p);
@@ -111,12 +114,12 @@ int geo_build_bins(const geo_mesh* mesh, const geo_level* lv, int32_t kind, int3
     if ((rc = geo_fill_i32(cnt, 0, nkeys, s)) != GEO_OK) return rc;
     if ((rc = launch_check_mesh(m, d, d_stats, s)) != GEO_OK) return rc;
     if (kind == GEO_BINS_ROWS)
-        rc = launch_rows_pass1(m, d, precision, cnt, pairs, out->cap, out->d_count, d_stats, s);
+        rc = launch_rows_pass1(m, d, precision, cnt, pairs, rank, out->cap, out->d_count, d_stats, s);
     else
-        rc = launch_links_pass1(m, d, cnt, pairs, out->cap, out->d_count, s);
+        rc = launch_links_pass1(m, d, cnt, pairs, rank, out->cap, out->d_count, s);
     if (rc != GEO_OK) return rc;
     if ((rc = geo_scan_exclusive(cnt, out->off, nkeys, partials, s)) != GEO_OK) return rc;
-    return launch_bins_scatter(pairs, out->cap, out->d_count, out->off, cnt, out->val, s);
+    return launch_bins_scatter(pairs, rank, out->cap, out->d_count, out->off, out->val, s);
 }
 
 int geo_voxelize(const geo_level* lv, const geo_bins* rows, uint64_t* solid, geo_stream_t stream) {

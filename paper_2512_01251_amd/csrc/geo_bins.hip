@@ -20,14 +20,17 @@ namespace {
 // Append of (key, value) pairs.  Each workgroup is one wave; pairs are staged
 // in an LDS buffer and flushed with one global reservation per flush (a
 // global counter touched once per wave-iteration would serialise at L2).
-// The per-key counts are incremented at flush time.
+// The per-key counts are incremented at flush time, and the count a pair
+// finds is its rank among its key's pairs, kept beside it: the scatter then
+// places it without atomics.
 // ------------------------------------------------------------------------
-constexpr int APP_BUF = 2048;
+constexpr int APP_BUF = 512;
 
 struct Appender {
     int2* buf;       // LDS [APP_BUF]
     int n;           // pairs staged (identical in every lane)
     int2* pairs;
+    int32_t* rank;
     int64_t cap;
     int64_t* d_count;
     int32_t* cnt;
@@ -38,11 +41,25 @@ struct Appender {
         unsigned long long base = 0;
         if (threadIdx.x == 0) base = atomicAdd((unsigned long long*)d_count, (unsigned long long)n);
         base = __shfl(base, 0, 64);
-        for (int i = threadIdx.x; i < n; i += 64) {
-            const int2 p = buf[i];
-            const unsigned long long pos = base + (unsigned long long)i;
-            if (pos < (unsigned long long)cap) pairs[pos] = p;
-            atomicAdd(&cnt[p.x], 1);
+        // four returning atomics in flight per lane before their results are used
+        for (int i0 = threadIdx.x; i0 < n; i0 += 256) {
+            int2 p[4];
+            int r[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int i = i0 + 64 * u;
+                p[u] = i < n ? buf[i] : make_int2(-1, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) r[u] = p[u].x >= 0 ? atomicAdd(&cnt[p[u].x], 1) : 0;
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const unsigned long long pos = base + (unsigned long long)(i0 + 64 * u);
+                if (p[u].x >= 0 && pos < (unsigned long long)cap) {
+                    pairs[pos] = p[u];
+                    rank[pos] = r[u];
+                }
+            }
         }
         __syncthreads();
         n = 0;
@@ -332,10 +349,10 @@ __device__ void row_events(const DevMesh& m, const RowTri<R>& T, double s, int m
 }
 
 template <typename R>
-__global__ void __launch_bounds__(64) k_rows_pass1(DevMesh m, DevLevel d, int32_t* cnt, int2* pairs,
+__global__ void __launch_bounds__(64) k_rows_pass1(DevMesh m, DevLevel d, int32_t* cnt, int2* pairs, int32_t* rank,
                                                    int64_t cap, int64_t* d_count, uint64_t* stats) {
     __shared__ int2 sbuf[APP_BUF];
-    Appender app{sbuf, 0, pairs, cap, d_count, cnt};
+    Appender app{sbuf, 0, pairs, rank, cap, d_count, cnt};
     const int L = d.level;
     const int nx = d.n0[0] << L, ny = d.n0[1] << L, nz = d.n0[2] << L;
     const double s = ldexp(1.0, L);
@@ -458,10 +475,10 @@ __device__ bool tri_box_overlap(const double c[3], double hs, const SatTri& T) {
     return true;
 }
 
-__global__ void __launch_bounds__(64) k_links_pass1(DevMesh m, DevLevel d, int32_t* cnt, int2* pairs,
+__global__ void __launch_bounds__(64) k_links_pass1(DevMesh m, DevLevel d, int32_t* cnt, int2* pairs, int32_t* rank,
                                                     int64_t cap, int64_t* d_count) {
     __shared__ int2 sbuf[APP_BUF];
-    Appender app{sbuf, 0, pairs, cap, d_count, cnt};
+    Appender app{sbuf, 0, pairs, rank, cap, d_count, cnt};
     const int L = d.level;
     const double h = ldexp(1.0, -L), bw = 4.0 * h;
     const int nbx = (d.n0[0] >> 2) << L, nby = (d.n0[1] >> 2) << L, nbz = (d.n0[2] >> 2) << L;
@@ -521,13 +538,13 @@ __global__ void __launch_bounds__(64) k_links_pass1(DevMesh m, DevLevel d, int32
     app.flush();
 }
 
-__global__ void k_bins_scatter(const int2* pairs, int64_t cap, const int64_t* d_count, const int32_t* off,
-                               int32_t* cursor, int32_t* val) {
+__global__ void k_bins_scatter(const int2* pairs, const int32_t* rank, int64_t cap, const int64_t* d_count,
+                               const int32_t* off, int32_t* val) {
     const int64_t n0 = *d_count;
     const int64_t n = n0 < cap ? n0 : cap;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int2 p = pairs[i];
-        const int64_t pos = (int64_t)off[p.x] + (atomicSub(&cursor[p.x], 1) - 1);
+        const int64_t pos = (int64_t)off[p.x] + rank[i];
         if (pos >= 0 && pos < cap) val[pos] = p.y;
     }
 }
@@ -554,33 +571,33 @@ inline unsigned grid_for(int64_t n, int threads, int64_t maxg = 1 << 16) {
 }  // namespace
 
 int launch_rows_pass1(const DevMesh& m, const DevLevel& d, int precision, int32_t* cnt, int2* pairs,
-                      int64_t cap, int64_t* d_count, uint64_t* d_stats, hipStream_t s) {
+                      int32_t* rank, int64_t cap, int64_t* d_count, uint64_t* d_stats, hipStream_t s) {
     if (m.nt == 0) return GEO_OK;
     const unsigned g = grid_for(m.nt, 64, 16384);
     kt_record(GEO_KT_ROWS, s, false);
     if (precision == GEO_PREC_F32_FALLBACK)
-        k_rows_pass1<float><<<g, 64, 0, s>>>(m, d, cnt, pairs, cap, d_count, d_stats);
+        k_rows_pass1<float><<<g, 64, 0, s>>>(m, d, cnt, pairs, rank, cap, d_count, d_stats);
     else
-        k_rows_pass1<double><<<g, 64, 0, s>>>(m, d, cnt, pairs, cap, d_count, d_stats);
+        k_rows_pass1<double><<<g, 64, 0, s>>>(m, d, cnt, pairs, rank, cap, d_count, d_stats);
     kt_record(GEO_KT_ROWS, s, true);
     GEO_LAUNCH_CHECK();
     return GEO_OK;
 }
 
-int launch_links_pass1(const DevMesh& m, const DevLevel& d, int32_t* cnt, int2* pairs, int64_t cap,
-                       int64_t* d_count, hipStream_t s) {
+int launch_links_pass1(const DevMesh& m, const DevLevel& d, int32_t* cnt, int2* pairs, int32_t* rank,
+                       int64_t cap, int64_t* d_count, hipStream_t s) {
     if (m.nt == 0) return GEO_OK;
     kt_record(GEO_KT_LINKS_BINS, s, false);
-    k_links_pass1<<<grid_for(m.nt, 64, 16384), 64, 0, s>>>(m, d, cnt, pairs, cap, d_count);
+    k_links_pass1<<<grid_for(m.nt, 64, 16384), 64, 0, s>>>(m, d, cnt, pairs, rank, cap, d_count);
     kt_record(GEO_KT_LINKS_BINS, s, true);
     GEO_LAUNCH_CHECK();
     return GEO_OK;
 }
 
-int launch_bins_scatter(const int2* pairs, int64_t cap, const int64_t* d_count, const int32_t* off,
-                        int32_t* cursor, int32_t* val, hipStream_t s) {
+int launch_bins_scatter(const int2* pairs, const int32_t* rank, int64_t cap, const int64_t* d_count,
+                        const int32_t* off, int32_t* val, hipStream_t s) {
     if (cap <= 0) return GEO_OK;
-    k_bins_scatter<<<grid_for(cap, 256, 8192), 256, 0, s>>>(pairs, cap, d_count, off, cursor, val);
+    k_bins_scatter<<<grid_for(cap, 256, 8192), 256, 0, s>>>(pairs, rank, cap, d_count, off, val);
     GEO_LAUNCH_CHECK();
     return GEO_OK;
 }

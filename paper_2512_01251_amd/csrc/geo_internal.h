@@ -267,11 +267,12 @@ int geo_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
 int geo_sum_i32(const int32_t* in, int64_t n, int64_t* out, hipStream_t s);
 
 int launch_rows_pass1(const DevMesh& m, const DevLevel& d, int precision, int32_t* cnt,
-                      int2* pairs, int64_t cap, int64_t* d_count, uint64_t* d_stats, hipStream_t s);
-int launch_links_pass1(const DevMesh& m, const DevLevel& d, int32_t* cnt, int2* pairs, int64_t cap,
-                       int64_t* d_count, hipStream_t s);
-int launch_bins_scatter(const int2* pairs, int64_t cap, const int64_t* d_count, const int32_t* off,
-                        int32_t* cursor, int32_t* val, hipStream_t s);
+                      int2* pairs, int32_t* rank, int64_t cap, int64_t* d_count, uint64_t* d_stats,
+                      hipStream_t s);
+int launch_links_pass1(const DevMesh& m, const DevLevel& d, int32_t* cnt, int2* pairs, int32_t* rank,
+                       int64_t cap, int64_t* d_count, hipStream_t s);
+int launch_bins_scatter(const int2* pairs, const int32_t* rank, int64_t cap, const int64_t* d_count,
+                        const int32_t* off, int32_t* val, hipStream_t s);
 int launch_check_mesh(const DevMesh& m, const DevLevel& d, uint64_t* d_stats, hipStream_t s);
 int launch_voxelize(const DevLevel& d, const int32_t* off, const int32_t* val, int64_t cap,
                     uint64_t* solid, hipStream_t s);
