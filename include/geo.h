@@ -31,7 +31,9 @@
  *  - Mesh contract (Methodology, "Overview" and "Voxelization and Near-Wall
  *    Refinement"): closed, oriented with outward normals (counter-clockwise
  *    seen from outside), not self-intersecting; every vertex coordinate lies in
- *    [2^-12, n0] or is 0.  Zero-area triangles are allowed and ignored.  A
+ *    [1/4, n0] or is 0 (then the cell-centre frame x 2^L - 1/2 of every
+ *    coordinate is exact in float64).  Zero-area triangles are allowed and
+ *    ignored.  A
  *    violation gives unspecified flags but never an out-of-bounds access;
  *    vertex-range violations are counted in d_stats[GEO_STAT_CONTRACT].
  *  - Results of geo_voxelize, geo_refine_flags and the integer outputs of

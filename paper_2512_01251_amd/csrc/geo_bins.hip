@@ -555,7 +555,7 @@ __global__ void k_check_mesh(DevMesh m, DevLevel d, uint64_t* stats) {
          i += (int64_t)gridDim.x * blockDim.x) {
         const int a = (int)(i % 3);
         const double x = load_coord(m, (int)(i / 3), a);
-        const bool ok = x == 0.0 || (x >= 0x1p-12 && x <= (double)d.n0[a]);
+        const bool ok = x == 0.0 || (x >= 0.25 && x <= (double)d.n0[a]);
         bad += ok ? 0u : 1u;
     }
     wave_count(&stats[GEO_STAT_CONTRACT], bad);

@@ -758,6 +758,8 @@ __global__ void __launch_bounds__(64) k_cl_fix(DevMesh m, DevLevel d, const int3
         int64_t c0 = loff[b], c1 = loff[b + 1];
         if (c1 > lcap) c1 = lcap;
         if (c0 < 0) c0 = 0;
+        const double slo[3] = {fmin(X[0], Y[0]), fmin(X[1], Y[1]), fmin(X[2], Y[2])};
+        const double shi[3] = {fmax(X[0], Y[0]), fmax(X[1], Y[1]), fmax(X[2], Y[2])};
         unsigned long long best = KEY_MISS;
         for (int64_t c = c0 + threadIdx.x; c < c1; c += 64) {
             const int tri = lval[c];
@@ -766,6 +768,12 @@ __global__ void __launch_bounds__(64) k_cl_fix(DevMesh m, DevLevel d, const int3
             vert_scaled(m, m.tris[3 * (int64_t)tri], s, A);
             vert_scaled(m, m.tris[3 * (int64_t)tri + 1], s, B);
             vert_scaled(m, m.tris[3 * (int64_t)tri + 2], s, Cc);
+            // boxes apart: no contact (the scaled coordinates are exact)
+            bool apart = false;
+#pragma unroll
+            for (int a = 0; a < 3; a++)
+                apart |= fmax(A[a], fmax(B[a], Cc[a])) < slo[a] || fmin(A[a], fmin(B[a], Cc[a])) > shi[a];
+            if (apart) continue;
             double tq;
             if (exact_seg_hit(A, B, Cc, X, Y, tq, st)) {
                 const unsigned long long kk = hit_key(tq, tri);

@@ -142,7 +142,7 @@ def _pts3(rng, n, scale):
             a, b, c = (np.round(p) for p in (a, b, c))
             d = np.round(rng.uniform(-scale, scale, 3))
         # the contract: coordinates are multiples of 2^-64 (true of every
-        # local coordinate the kernels form from vertices >= 2^-12)
+        # local coordinate the kernels form from vertices in [1/4, n0])
         snap = lambda p: np.ldexp(np.round(np.ldexp(p, 52)), -52)
         out.append(tuple(snap(p) for p in (a, b, c, d)))
     return out
