@@ -761,23 +761,40 @@ __global__ void __launch_bounds__(64) k_cl_fix(DevMesh m, DevLevel d, const int3
         const double slo[3] = {fmin(X[0], Y[0]), fmin(X[1], Y[1]), fmin(X[2], Y[2])};
         const double shi[3] = {fmax(X[0], Y[0]), fmax(X[1], Y[1]), fmax(X[2], Y[2])};
         unsigned long long best = KEY_MISS;
-        for (int64_t c = c0 + threadIdx.x; c < c1; c += 64) {
-            const int tri = lval[c];
-            if ((unsigned)tri >= (unsigned)m.nt) continue;  // entry of an overflowed bin
-            double A[3], B[3], Cc[3];
-            vert_scaled(m, m.tris[3 * (int64_t)tri], s, A);
-            vert_scaled(m, m.tris[3 * (int64_t)tri + 1], s, B);
-            vert_scaled(m, m.tris[3 * (int64_t)tri + 2], s, Cc);
-            // boxes apart: no contact (the scaled coordinates are exact)
-            bool apart = false;
+        // four candidates per lane and round: their triangle and vertex ids are
+        // loaded together, the coordinates just before each test
+        for (int64_t cb = c0 + threadIdx.x; cb < c1; cb += 256) {
+            int tri[4], vid[4][3];
 #pragma unroll
-            for (int a = 0; a < 3; a++)
-                apart |= fmax(A[a], fmax(B[a], Cc[a])) < slo[a] || fmin(A[a], fmin(B[a], Cc[a])) > shi[a];
-            if (apart) continue;
-            double tq;
-            if (exact_seg_hit(A, B, Cc, X, Y, tq, st)) {
-                const unsigned long long kk = hit_key(tq, tri);
-                best = kk < best ? kk : best;
+            for (int u = 0; u < 4; u++) {
+                const int64_t c = cb + 64 * u;
+                tri[u] = c < c1 ? lval[c] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                // entries of an overflowed bin are not triangle ids
+                const bool ok = (unsigned)tri[u] < (unsigned)m.nt;
+#pragma unroll
+                for (int i = 0; i < 3; i++) vid[u][i] = ok ? m.tris[3 * (int64_t)tri[u] + i] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                if (vid[u][0] < 0) continue;
+                double A[3], B[3], Cc[3];
+                vert_scaled(m, vid[u][0], s, A);
+                vert_scaled(m, vid[u][1], s, B);
+                vert_scaled(m, vid[u][2], s, Cc);
+                // boxes apart: no contact (the scaled coordinates are exact)
+                bool apart = false;
+#pragma unroll
+                for (int a = 0; a < 3; a++)
+                    apart |= fmax(A[a], fmax(B[a], Cc[a])) < slo[a] || fmin(A[a], fmin(B[a], Cc[a])) > shi[a];
+                if (apart) continue;
+                double tq;
+                if (exact_seg_hit(A, B, Cc, X, Y, tq, st)) {
+                    const unsigned long long kk = hit_key(tq, tri[u]);
+                    best = kk < best ? kk : best;
+                }
             }
         }
 #pragma unroll
