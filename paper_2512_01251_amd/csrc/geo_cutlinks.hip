@@ -263,6 +263,8 @@ __device__ void stage_cand(const DevMesh& m, int L, int tri, const int vid[3], c
         for (int a = 0; a < 3; a++) { lo[a] = -1e30f; hi[a] = 1e30f; }
     }
     B.lo = make_float4(lo[0], lo[1], lo[2], (float)flags);
+    // the filtered test never decides such a candidate
+    if (flags & C_SLOW) C.bound = (R)INFINITY;
     B.hi = make_float4(hi[0], hi[1], hi[2], 0.0f);
 }
 
@@ -510,13 +512,12 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
     // position j in -1..4, bmask[12a + 1 + j] holds the candidates with
     // hi_a >= j and bmask[12a + 7 + j] those with lo_a <= j
     __shared__ unsigned long long bmask[36];
-    __shared__ uint8_t cflag[CL_CAND];
     __shared__ uint32_t smask[64];
     __shared__ int spre[65];
     __shared__ unsigned halo[36];
     __shared__ uint16_t flat[64 * CL_MAXC];   // flattened pairs: owner lane | candidate slot << 6
     __shared__ unsigned long long lbest[64];  // nearest hit of each lane's link (packed key)
-    __shared__ int sk[64];                    // link (t, k) of each lane, packed t | k << 8
+    __shared__ int sk[64];                    // link of each lane: t | (d + 1) << 8 (2 bits per axis)
     const int L = d.level;
     const int lane = threadIdx.x;
     const uint32_t dirs = lattice_dirs(lattice);
@@ -586,7 +587,6 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
                 }
                 CBox bx;
                 stage_cand<R>(m, L, tri, vid, b0, cand[lane], bx);
-                cflag[lane] = (uint8_t)bx.lo.w;
                 blo[0] = bx.lo.x; blo[1] = bx.lo.y; blo[2] = bx.lo.z;
                 bhi[0] = bx.hi.x; bhi[1] = bx.hi.y; bhi[2] = bx.hi.z;
                 st.staged++;
@@ -637,9 +637,9 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
             for (int q = 0; q < r; q++) mm &= mm - 1u;
             k = __ffs(mm) - 1;
         }
-        sk[lane] = t | (k << 8);
         int cx, cy, cz;
         dirvec(k, cx, cy, cz);
+        sk[lane] = t | ((cx + 1) << 8) | ((cy + 1) << 10) | ((cz + 1) << 12);
         const int slo[3] = {geo_min(t & 3, (t & 3) + cx), geo_min((t >> 2) & 3, ((t >> 2) & 3) + cy),
                             geo_min(t >> 4, (t >> 4) + cz)};
         const int shi[3] = {geo_max(t & 3, (t & 3) + cx), geo_max((t >> 2) & 3, ((t >> 2) & 3) + cy),
@@ -677,16 +677,13 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
                 const int ow = fe & 63;
                 const int cidx = fe >> 6;
                 const int tk = sk[ow];
-                const int ot = tk & 0xff, ok = tk >> 8;
-                int ox, oy, oz;
-                dirvec(ok, ox, oy, oz);
-                const int Xi[3] = {ot & 3, (ot >> 2) & 3, ot >> 4};
+                const int ox = ((tk >> 8) & 3) - 1, oy = ((tk >> 10) & 3) - 1, oz = ((tk >> 12) & 3) - 1;
+                const int Xi[3] = {tk & 3, (tk >> 2) & 3, (tk >> 4) & 3};
                 const R X[3] = {(R)Xi[0], (R)Xi[1], (R)Xi[2]};
                 const R Y[3] = {(R)(Xi[0] + ox), (R)(Xi[1] + oy), (R)(Xi[2] + oz)};
                 const Cand<R>& C = cand[cidx];
-                const int flags = cflag[cidx];
                 R tr = 0, terr = 0;
-                const int res = (flags & C_SLOW) ? -1 : fast_test<R>(C, X, Y, tr, terr);
+                const int res = fast_test<R>(C, X, Y, tr, terr);
                 unsigned long long kk = KEY_MISS;
                 if (res == 1) {
                     // hit parameter from the float64 plane
