@@ -442,8 +442,9 @@ __device__ __forceinline__ void sat_setup(SatTri& T) {
 
 // Conservative triangle / cube overlap (centre c, half side hs): separating
 // axes are the box normals, the triangle normal and the nine edge crosses,
-// each with a relative margin that covers the rounding of the test.
-__device__ bool tri_box_overlap(const double c[3], double hs, const SatTri& T) {
+// each with a relative margin that covers the rounding of the test.  Stage
+// one takes the box normals and the triangle normal, stage two the edges.
+__device__ bool tri_box_stage1(const double c[3], double hs, const SatTri& T) {
     for (int a = 0; a < 3; a++)
         if (axis_sep(T.v[0][a] - c[a], T.v[1][a] - c[a], T.v[2][a] - c[a], hs)) return false;
     // the normal axis: projections n . v_i - n . c against the box radius; the
@@ -451,7 +452,10 @@ __device__ bool tri_box_overlap(const double c[3], double hs, const SatTri& T) {
     const double nc = T.n[0] * c[0] + T.n[1] * c[1] + T.n[2] * c[2];
     const double err = 5e-16 * (T.nvabs + fabs(T.n[0] * c[0]) + fabs(T.n[1] * c[1]) + fabs(T.n[2] * c[2]));
     const double rn = hs * T.n1 * (1.0 + 1e-9) + 1e-12 * T.n1 + err;
-    if (T.nvmin - nc > rn || T.nvmax - nc < -rn) return false;
+    return !(T.nvmin - nc > rn || T.nvmax - nc < -rn);
+}
+
+__device__ bool tri_box_stage2(const double c[3], double hs, const SatTri& T) {
     double v0[3], v1[3], v2[3];
     for (int a = 0; a < 3; a++) {
         v0[a] = T.v[0][a] - c[a];
@@ -517,18 +521,55 @@ __global__ void __launch_bounds__(64) k_links_pass1(DevMesh m, DevLevel d, int32
             }
         }
         const int sx = hi[0] - lo[0] + 1, sy = hi[1] - lo[1] + 1, sz = hi[2] - lo[2] + 1;
-        const int n = (sx > 0 && sy > 0 && sz > 0) ? sx * sy * sz : 0;
-        for (int it = 0; __any(it < n); it++) {
+        const int64_t n = (sx > 0 && sy > 0 && sz > 0) ? (int64_t)sx * sy * sz : 0;
+        const double hs = (0.5 * bw + 0.5 * h) * (1.0 + 1e-9);
+        // candidate block it of the triangle: box [4bh - h/2, 4(b+1)h + h/2]
+        // reached by the block's links, plus a relative margin
+        auto centre = [&](int64_t it, int b[3], double c[3]) {
+            b[0] = lo[0] + (int)(it % sx);
+            b[1] = lo[1] + (int)((it / sx) % sy);
+            b[2] = lo[2] + (int)(it / ((int64_t)sx * sy));
+            for (int a = 0; a < 3; a++) c[a] = (b[a] + 0.5) * bw;
+        };
+        // the first 32 candidates: cheap axes first, into a bit mask, then the
+        // edge axes over the survivors only (the wave iterates as often as
+        // its lane with the most survivors, not with the most candidates)
+        const int n32 = n < 32 ? (int)n : 32;
+        uint32_t pass1 = 0;
+        for (int it = 0; __any(it < n32); it++) {
+            if (it < n32) {
+                int b[3];
+                double c[3];
+                centre(it, b, c);
+                if (tri_box_stage1(c, hs, T)) pass1 |= 1u << it;
+            }
+        }
+        while (__any(pass1 != 0)) {
+            bool has = false;
+            int key = 0;
+            if (pass1) {
+                const int it = __ffs(pass1) - 1;
+                pass1 &= pass1 - 1;
+                int b[3];
+                double c[3];
+                centre(it, b, c);
+                if (tri_box_stage2(c, hs, T)) {
+                    key = forest_lookup(d, b[0], b[1], b[2]);
+                    has = key >= 0;
+                }
+            }
+            app.add(has, key, (int32_t)t);
+        }
+        // candidates beyond the first 32 (large triangles): both stages at once
+        for (int64_t it = 32; __any(it < n); it++) {
             bool has = false;
             int key = 0;
             if (it < n) {
-                const int bx = lo[0] + it % sx, by = lo[1] + (it / sx) % sy, bz = lo[2] + it / (sx * sy);
-                // box [4bh - h/2, 4(b+1)h + h/2] reached by the block's links,
-                // plus a relative margin; the block is looked up only on overlap
-                const double c[3] = {(bx + 0.5) * bw, (by + 0.5) * bw, (bz + 0.5) * bw};
-                const double hs = (0.5 * bw + 0.5 * h) * (1.0 + 1e-9);
-                if (tri_box_overlap(c, hs, T)) {
-                    key = forest_lookup(d, bx, by, bz);
+                int b[3];
+                double c[3];
+                centre(it, b, c);
+                if (tri_box_stage1(c, hs, T) && tri_box_stage2(c, hs, T)) {
+                    key = forest_lookup(d, b[0], b[1], b[2]);
                     has = key >= 0;
                 }
             }
