@@ -26,6 +26,10 @@ namespace {
 // ------------------------------------------------------------------------
 constexpr int APP_BUF = 512;
 
+// Group: pairs whose keys repeat within a flush (link bins: neighbouring
+// triangles share blocks) take their ranks with one atomic per key; else one
+// atomic per pair (row bins: keys mostly distinct).
+template <bool Group>
 struct Appender {
     int2* buf;       // LDS [APP_BUF]
     int n;           // pairs staged (identical in every lane)
@@ -41,23 +45,69 @@ struct Appender {
         unsigned long long base = 0;
         if (threadIdx.x == 0) base = atomicAdd((unsigned long long*)d_count, (unsigned long long)n);
         base = __shfl(base, 0, 64);
-        // four returning atomics in flight per lane before their results are used
-        for (int i0 = threadIdx.x; i0 < n; i0 += 256) {
-            int2 p[4];
-            int r[4];
+        if constexpr (Group) {
+            // Per chunk of 64 pairs, lanes holding the same key form a group;
+            // its lowest lane takes the group's ranks with one atomic (atomics
+            // on one address serialise).  The atomics of four chunks are in
+            // flight together.
+            const int lane = threadIdx.x;
+            const unsigned long long lt = (1ull << lane) - 1ull;
+            for (int i0 = 0; i0 < n; i0 += 256) {
+                int2 p[4];
+                int lead[4], off[4], cntk[4];
 #pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const int i = i0 + 64 * u;
-                p[u] = i < n ? buf[i] : make_int2(-1, 0);
+                for (int u = 0; u < 4; u++) {
+                    const int i = i0 + 64 * u + lane;
+                    const bool valid = i < n;
+                    p[u] = valid ? buf[i] : make_int2(-1, 0);
+                    lead[u] = -1;
+                    off[u] = 0;
+                    cntk[u] = 0;
+                    unsigned long long rem = __ballot(valid);
+                    while (rem) {  // uniform
+                        const int l = __ffsll(rem) - 1;
+                        const int k = __shfl(p[u].x, l, 64);
+                        const unsigned long long same = __ballot(valid && p[u].x == k) & rem;
+                        if ((same >> lane) & 1ull) {
+                            lead[u] = l;
+                            off[u] = __popcll(same & lt);
+                        }
+                        if (lane == l) cntk[u] = __popcll(same);
+                        rem &= ~same;
+                    }
+                }
+                int r[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) r[u] = cntk[u] ? atomicAdd(&cnt[p[u].x], cntk[u]) : 0;
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int base_k = __shfl(r[u], lead[u] < 0 ? lane : lead[u], 64);
+                    const unsigned long long pos = base + (unsigned long long)(i0 + 64 * u + lane);
+                    if (p[u].x >= 0 && pos < (unsigned long long)cap) {
+                        pairs[pos] = p[u];
+                        rank[pos] = base_k + off[u];
+                    }
+                }
             }
+        } else {
+            // four returning atomics in flight per lane before their results are used
+            for (int i0 = threadIdx.x; i0 < n; i0 += 256) {
+                int2 p[4];
+                int r[4];
 #pragma unroll
-            for (int u = 0; u < 4; u++) r[u] = p[u].x >= 0 ? atomicAdd(&cnt[p[u].x], 1) : 0;
+                for (int u = 0; u < 4; u++) {
+                    const int i = i0 + 64 * u;
+                    p[u] = i < n ? buf[i] : make_int2(-1, 0);
+                }
 #pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const unsigned long long pos = base + (unsigned long long)(i0 + 64 * u);
-                if (p[u].x >= 0 && pos < (unsigned long long)cap) {
-                    pairs[pos] = p[u];
-                    rank[pos] = r[u];
+                for (int u = 0; u < 4; u++) r[u] = p[u].x >= 0 ? atomicAdd(&cnt[p[u].x], 1) : 0;
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const unsigned long long pos = base + (unsigned long long)(i0 + 64 * u);
+                    if (p[u].x >= 0 && pos < (unsigned long long)cap) {
+                        pairs[pos] = p[u];
+                        rank[pos] = r[u];
+                    }
                 }
             }
         }
@@ -352,7 +402,7 @@ template <typename R>
 __global__ void __launch_bounds__(64) k_rows_pass1(DevMesh m, DevLevel d, int32_t* cnt, int2* pairs, int32_t* rank,
                                                    int64_t cap, int64_t* d_count, uint64_t* stats) {
     __shared__ int2 sbuf[APP_BUF];
-    Appender app{sbuf, 0, pairs, rank, cap, d_count, cnt};
+    Appender<false> app{sbuf, 0, pairs, rank, cap, d_count, cnt};
     const int L = d.level;
     const int nx = d.n0[0] << L, ny = d.n0[1] << L, nz = d.n0[2] << L;
     const double s = ldexp(1.0, L);
@@ -482,7 +532,7 @@ __device__ bool tri_box_stage2(const double c[3], double hs, const SatTri& T) {
 __global__ void __launch_bounds__(64) k_links_pass1(DevMesh m, DevLevel d, int32_t* cnt, int2* pairs, int32_t* rank,
                                                     int64_t cap, int64_t* d_count) {
     __shared__ int2 sbuf[APP_BUF];
-    Appender app{sbuf, 0, pairs, rank, cap, d_count, cnt};
+    Appender<true> app{sbuf, 0, pairs, rank, cap, d_count, cnt};
     const int L = d.level;
     const double h = ldexp(1.0, -L), bw = 4.0 * h;
     const int nbx = (d.n0[0] >> 2) << L, nby = (d.n0[1] >> 2) << L, nbz = (d.n0[2] >> 2) << L;
