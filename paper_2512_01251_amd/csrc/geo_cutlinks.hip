@@ -114,20 +114,38 @@ __global__ void __launch_bounds__(64) k_cl_mask(DevLevel d, const int32_t* off, 
                                                 int32_t* blk_cnt) {
     __shared__ unsigned halo[36];
     const uint32_t dirs = lattice_dirs(lattice);
-    for (int64_t b = blockIdx.x; b < d.nblocks; b += gridDim.x) {
+    const int lane = threadIdx.x;
+    const int64_t nchunks = (d.nblocks + 63) / 64;
+    // chunks of 64 blocks: one coalesced read of their candidate counts, then
+    // only the blocks with candidates are classified, one per wave step
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int64_t b0 = ch * 64;
+        const int64_t bl = b0 + lane;
+        const bool inb = bl < d.nblocks;
         // a cut link crosses the surface inside the block's reach, so a block
-        // without candidate triangles has none (uniform branch)
-        if (loff[b] == loff[b + 1]) {
-            if (link_mask) link_mask[64 * b + threadIdx.x] = 0;
-            if (threadIdx.x == 0) blk_cnt[b] = 0;
-            continue;
-        }
-        const uint32_t m = block_link_mask(d, off, val, cap, dirs, b, halo);
-        if (link_mask) link_mask[64 * b + threadIdx.x] = m;
-        int c = __popc(m);
+        // without candidate triangles has none
+        const bool has = inb && loff[bl] != loff[bl + 1];
+        if (inb && !has) blk_cnt[bl] = 0;
+        unsigned long long todo = __ballot(has);
+        while (todo) {  // uniform
+            const int i = __ffsll(todo) - 1;
+            todo &= todo - 1;
+            const int64_t b = b0 + i;
+            const uint32_t m = block_link_mask(d, off, val, cap, dirs, b, halo);
+            if (link_mask) link_mask[64 * b + lane] = m;
+            int c = __popc(m);
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-        if (threadIdx.x == 0) blk_cnt[b] = c;
+            for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+            if (lane == 0) blk_cnt[b] = c;
+        }
+        if (link_mask) {
+            unsigned long long empty = __ballot(inb && !has);
+            while (empty) {  // uniform
+                const int i = __ffsll(empty) - 1;
+                empty &= empty - 1;
+                link_mask[64 * (b0 + i) + lane] = 0;
+            }
+        }
     }
 }
 
@@ -845,7 +863,8 @@ int launch_cutlinks(const DevMesh& m, const DevLevel& d, const geo_bins* rows, c
     p += al(sizeof(int32_t) * c);
     int32_t* fixn = reinterpret_cast<int32_t*>(p);
     if (nb == 0) return geo_fill_u64(reinterpret_cast<uint64_t*>(d_nlinks), 0, 1, s);
-    const unsigned g = (unsigned)(nb < 262144 ? nb : 262144);
+    const int64_t nchunk = (nb + 63) / 64;
+    const unsigned g = (unsigned)(nchunk < 32768 ? nchunk : 32768);
     k_cl_mask<<<g, 64, 0, s>>>(d, rows->off, rows->val, rows->cap, links->off, lattice, link_mask, blk_cnt);
     GEO_LAUNCH_CHECK();
     // exact link count (the table's offsets are int32)
