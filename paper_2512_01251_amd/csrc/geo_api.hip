@@ -26,8 +26,11 @@ bool check_level(const geo_level* lv) {
     }
     if (lv->nblocks > 0 && !lv->bcoord) return false;
     if ((int64_t)lv->nblocks * 64 > INT32_MAX) return false;
-    for (int l = 0; l < lv->level; l++)
-        if (!lv->child[l]) return false;
+    // the child maps are read only through the blocks of this level (a level
+    // without blocks may follow one without refined blocks)
+    if (lv->nblocks > 0)
+        for (int l = 0; l < lv->level; l++)
+            if (!lv->child[l]) return false;
     return true;
 }
 

@@ -210,3 +210,23 @@ def test_smoke_workload_and_its_oracle_reference_build():
     w = ge.smoke_workload()
     ref = oracle.embed(w.mesh, w.n0, w.lf, w.lattice, w.d_spec)
     assert ref["links"]["n"] > 0 and len(ref["levels"]) == w.lf + 1
+
+
+def test_level_without_blocks_needs_no_child_maps(geo):
+    # a level that follows one without refined blocks has no blocks and no
+    # valid child maps; calls on it are accepted and enqueue nothing
+    L = geo.lib()
+    lv = geo.geo_level()
+    for a in range(3):
+        lv.n0[a] = 32
+    lv.level = 2
+    lv.nblocks = 0
+    nkeys = (32 << 2) * (32 << 2)
+    off = (C.c_int32 * 1)()
+    cnt = (C.c_int64 * 1)()
+    bins = geo.geo_bins(geo.GEO_BINS_ROWS, nkeys, C.addressof(off), None, 0, C.addressof(cnt))
+    assert L.geo_voxelize(C.byref(lv), C.byref(bins), None, None) == geo.GEO_OK
+    lv.nblocks = 5              # with blocks, the coarser child maps are required
+    bc = (C.c_int32 * 15)()
+    lv.bcoord = C.addressof(bc)
+    assert L.geo_voxelize(C.byref(lv), C.byref(bins), None, None) == geo.GEO_ERR_ARG
