@@ -138,3 +138,57 @@ def test_star7m_sampled(c2, precision):
     st = emb.stats.cpu().numpy()
     say(f"[fullsize] star7m {precision} ok: {emb.links.n} links, sampled max |dq| {e:.2e}, stats {st.tolist()}")
     assert st[3] == 0
+
+
+# ----------------------------------------------------------------------------
+# degenerate and multi-body workloads at full size (256^3 base, levels 0..3,
+# D3Q19): faces and vertices on cell-centre planes and lattice points, and 64
+# disjoint bodies
+# ----------------------------------------------------------------------------
+
+_deg_cache = {}
+
+
+def _deg_ref(name):
+    if name not in _deg_cache:
+        w = configs.get(name)
+        say(f"[fullsize] {name} oracle ...")
+        _deg_cache[name] = (w, oracle.embed(w.mesh, w.n0, w.lf, w.lattice, w.d_spec))
+    return _deg_cache[name]
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+@pytest.mark.parametrize("name", ["box256", "prism256"])
+def test_degenerate_fullsize_exact(name, precision):
+    from gpu_helpers import compare
+    w, ref = _deg_ref(name)
+    say(f"[fullsize] {name} {precision}")
+    emb, _, _ = gpu_embed(w, precision)
+    s = compare(w, emb, ref)
+    _check_invariants(w, emb)
+    say(f"[fullsize] {name} {precision} ok {s}")
+    assert emb.stats.cpu().numpy()[3] == 0
+
+
+@pytest.fixture(scope="module")
+def c4():
+    w = configs.spheres64()
+    say("[fullsize] spheres64 oracle forest ...")
+    return w, oracle.embed(w.mesh, w.n0, w.lf, w.lattice, w.d_spec, with_links=False)
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_spheres64_forest_exact_and_links_sampled(c4, precision):
+    w, ref = c4
+    say(f"[fullsize] spheres64 {precision}")
+    emb, _, _ = gpu_embed(w, precision)
+    for g, r in zip(emb.levels, ref["levels"]):
+        assert np.array_equal(g.bcoord.cpu().numpy(), r["bcoord"])
+        assert np.array_equal(g.solid.cpu().numpy().view(np.uint64), r["solid"]), f"solid L{r['level']}"
+        if "refine" in r:
+            assert np.array_equal(g.bclass.cpu().numpy(), r["bclass"])
+            assert np.array_equal(g.refine.cpu().numpy(), r["refine"])
+            assert np.array_equal(g.child_map.cpu().numpy(), r["child_map"])
+    _check_invariants(w, emb)
+    e = _check_links_sample(w, emb, np.random.default_rng(5), 20000)
+    say(f"[fullsize] spheres64 {precision} ok: {emb.links.n} links, sampled max |dq| {e:.2e}")
