@@ -265,6 +265,23 @@ def main():
         "stats_f32": dict(zip(["f32_to_f64", "exact", "links_exact", "contract", "staged", "pairs", "tasks"], stats)),
         **res64,
     }
+    # the paper's dense per-block layout of the table (a solver-facing view,
+    # outside the step): time and bytes written / read
+    from paper_2512_01251_amd.pipeline import links_dense
+    caps = {}
+    links_dense(out, caps)
+    s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    s_ev.record()
+    for _ in range(reps):
+        dn = links_dense(out, caps)
+    e_ev.record()
+    _sync()
+    dms = s_ev.elapsed_time(e_ev) / reps
+    qd = dn.q.shape[1]
+    dbytes = dn.nbnd * qd * 64 * 8 + 4 * dn.block_map.numel() + 13 * n_links
+    line["dense_layout"] = {"ms": dms, "boundary_blocks": dn.nbnd, "directions": qd, "bytes": dbytes,
+                            "gb_per_s": dbytes / (dms * 1e-3) / 1e9}
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, out, with_links=args.cpu_links)

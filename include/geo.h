@@ -64,7 +64,13 @@ enum { GEO_PREC_F64 = 0, GEO_PREC_F32_FALLBACK = 1 }; /* arithmetic form        
 enum { GEO_BINS_ROWS = 0, GEO_BINS_LINKS = 1 };    /* kind of bins             */
 
 /* workspace query selectors */
-enum { GEO_CALL_BINS_ROWS = 0, GEO_CALL_BINS_LINKS = 1, GEO_CALL_REFINE = 2, GEO_CALL_CUTLINKS = 3 };
+enum {
+    GEO_CALL_BINS_ROWS = 0,
+    GEO_CALL_BINS_LINKS = 1,
+    GEO_CALL_REFINE = 2,
+    GEO_CALL_CUTLINKS = 3,
+    GEO_CALL_LINKS_DENSE = 4 /* nkeys = blocks of the level, cap ignored */
+};
 
 /* device statistics counters (uint64 each) */
 enum {
@@ -206,6 +212,31 @@ int geo_cutlinks(const geo_mesh* mesh, const geo_level* lv, const geo_bins* rows
                  int64_t cap, int64_t* d_nlinks, int32_t* link_cell, uint8_t* link_dir,
                  float* link_q, int32_t* link_tri, uint64_t* d_stats, void* ws, size_t ws_bytes,
                  geo_stream_t stream);
+
+/*
+ * Dense per-block layout of a cut-link table (Methodology, "Memory
+ * Allocations for Boundary Cells"): the layout a block-structured solver
+ * reads.  A boundary block is a block of the level with at least one link.
+ *   block_map[b] (device int32[nblocks], written): index of block b among the
+ *     boundary blocks in block order, or -1;
+ *   dense_q[(j * Q + s) * 64 + t] (device float[cap * Q * 64], written): q of
+ *     the link of cell t of the j-th boundary block in the s-th direction of
+ *     the lattice (Q = 18 for D3Q19, 26 for D3Q27; directions in increasing k,
+ *     the rest direction left out), -1 where that cell has no link there;
+ *   dense_tri: same layout, int32, the hit triangle (the face whose boundary
+ *     condition applies), -1 where there is no link;
+ *   *d_nbnd (device int64) = number of boundary blocks; boundary blocks with
+ *     index >= cap are mapped but their entries are not written.
+ * The link arrays are a table of geo_cutlinks, sorted by block as
+ * geo_cutlinks writes it (another order gives unspecified entries, never an
+ * access out of bounds).  dense_q and dense_tri must be 16-byte aligned.
+ * Workspace: geo_workspace_size(GEO_CALL_LINKS_DENSE, nblocks, 0).
+ */
+int geo_links_dense(const geo_level* lv, int64_t n_links, const int32_t* link_cell,
+                    const uint8_t* link_dir, const float* link_q, const int32_t* link_tri,
+                    int32_t lattice, int64_t cap, int32_t* block_map, float* dense_q,
+                    int32_t* dense_tri, int64_t* d_nbnd, void* ws, size_t ws_bytes,
+                    geo_stream_t stream);
 
 /*
  * Backward of q with respect to the vertices (not in the paper): for each

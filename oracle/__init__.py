@@ -236,6 +236,39 @@ def grad(mesh, n0, L: int, bcoord: np.ndarray, link_cell, link_dir, link_tri, w)
     return g
 
 
+def lattice_dirs(lattice: int) -> np.ndarray:
+    """Directions k = (cx+1) + 3(cy+1) + 9(cz+1) of D3Q19 (|c|^2 <= 2) or
+    D3Q27, rest direction k = 13 left out, in increasing k."""
+    ks = []
+    for k in range(27):
+        c = np.array([k % 3 - 1, (k // 3) % 3 - 1, k // 9 - 1])
+        if k != 13 and (lattice == 27 or (c * c).sum() <= 2):
+            ks.append(k)
+    return np.array(ks)
+
+
+def links_dense(nblocks: int, link_cell, link_dir, link_q, link_tri, lattice: int) -> dict:
+    """Dense per-block layout of a link table (Methodology, "Memory
+    Allocations for Boundary Cells"): boundary blocks are the blocks with at
+    least one link, numbered in block order; block_map[b] is that number or
+    -1.  q and tri are [nbnd, Q, 64] (direction s = position of the link's k
+    among the lattice's directions, cell t), -1 where there is no link."""
+    cell = np.asarray(link_cell, dtype=np.int64)
+    blocks = np.unique(cell // 64)
+    block_map = np.full(nblocks, -1, np.int32)
+    block_map[blocks] = np.arange(len(blocks), dtype=np.int32)
+    dirs = lattice_dirs(lattice)
+    slot = np.full(27, -1, np.int64)
+    slot[dirs] = np.arange(len(dirs))
+    q = np.full((len(blocks), len(dirs), 64), -1.0, np.float32)
+    tri = np.full((len(blocks), len(dirs), 64), -1, np.int32)
+    j = block_map[cell // 64]
+    s = slot[np.asarray(link_dir, dtype=np.int64)]
+    q[j, s, cell % 64] = np.asarray(link_q, dtype=np.float32)
+    tri[j, s, cell % 64] = np.asarray(link_tri, dtype=np.int32)
+    return {"block_map": block_map, "q": q, "tri": tri}
+
+
 # ----------------------------------------------------------------------------
 # the whole path, level by level
 # ----------------------------------------------------------------------------

@@ -19,7 +19,7 @@ GEO_OK, GEO_ERR_ARG, GEO_ERR_WORKSPACE, GEO_ERR_DEVICE = 0, -1, -2, -3
 GEO_F32, GEO_F64 = 0, 1
 GEO_PREC_F64, GEO_PREC_F32_FALLBACK = 0, 1
 GEO_BINS_ROWS, GEO_BINS_LINKS = 0, 1
-GEO_CALL_BINS_ROWS, GEO_CALL_BINS_LINKS, GEO_CALL_REFINE, GEO_CALL_CUTLINKS = 0, 1, 2, 3
+GEO_CALL_BINS_ROWS, GEO_CALL_BINS_LINKS, GEO_CALL_REFINE, GEO_CALL_CUTLINKS, GEO_CALL_LINKS_DENSE = 0, 1, 2, 3, 4
 GEO_STAT_F32_TO_F64, GEO_STAT_EXACT, GEO_STAT_LINKS_EXACT, GEO_STAT_CONTRACT, GEO_STAT_STAGED, GEO_STAT_PAIRS = 0, 1, 2, 3, 4, 5
 GEO_STAT_TASKS = 6
 GEO_NSTATS = 7
@@ -29,7 +29,7 @@ GEO_MAX_LEVELS = 12
 GEO_MAX_RES = 32767
 
 EXPORTS = ["geo_workspace_size", "geo_nprop", "geo_level0_blocks", "geo_build_bins", "geo_voxelize",
-           "geo_refine_flags", "geo_cutlinks", "geo_cutlinks_backward", "geo_kernel_timer", "geo_kernel_timer_read", "geo_version"]
+           "geo_refine_flags", "geo_cutlinks", "geo_cutlinks_backward", "geo_links_dense", "geo_kernel_timer", "geo_kernel_timer_read", "geo_version"]
 
 
 class GeoError(RuntimeError):
@@ -73,6 +73,7 @@ def lib():
         L.geo_refine_flags.argtypes = [LP, P, i32, P, P, P, P, P, P, sz, P]
         L.geo_cutlinks.argtypes = [MP, LP, BP, BP, i32, i32, P, i64, P, P, P, P, P, P, P, sz, P]
         L.geo_cutlinks_backward.argtypes = [MP, LP, i64, P, P, P, P, P, P]
+        L.geo_links_dense.argtypes = [LP, i64, P, P, P, P, i32, i64, P, P, P, P, P, sz, P]
         L.geo_kernel_timer.argtypes = [i32, i32]
         L.geo_kernel_timer_read.argtypes = [i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.geo_version.restype = C.c_char_p
@@ -188,6 +189,15 @@ def geo_cutlinks(mesh: geo_mesh, level: geo_level, rows: geo_bins, links: geo_bi
                             _ptr(link_dir), _ptr(link_q), _ptr(link_tri), _ptr(stats), _ptr(ws),
                             ws.numel() if ws is not None else 0, _stream(stream))
     _check(rc, "geo_cutlinks")
+
+
+def geo_links_dense(level: geo_level, n_links: int, link_cell, link_dir, link_q, link_tri, lattice: int,
+                    cap: int, block_map, dense_q, dense_tri, d_nbnd, ws, stream=None):
+    rc = lib().geo_links_dense(C.byref(level), int(n_links), _ptr(link_cell), _ptr(link_dir), _ptr(link_q),
+                               _ptr(link_tri), int(lattice), int(cap), _ptr(block_map), _ptr(dense_q),
+                               _ptr(dense_tri), _ptr(d_nbnd), _ptr(ws), ws.numel() if ws is not None else 0,
+                               _stream(stream))
+    _check(rc, "geo_links_dense")
 
 
 def geo_cutlinks_backward(mesh: geo_mesh, level: geo_level, n_links: int, link_cell, link_dir,

@@ -65,6 +65,7 @@ size_t geo_workspace_size(int32_t call, int64_t nkeys, int64_t cap) {
         case GEO_CALL_BINS_LINKS: return bins_ws_bytes(nkeys, cap);
         case GEO_CALL_REFINE: return geo_refine_ws_bytes(nkeys);
         case GEO_CALL_CUTLINKS: return geo_cutlinks_ws_bytes(nkeys, cap);
+        case GEO_CALL_LINKS_DENSE: return geo_dense_ws_bytes(nkeys);
         default: return 0;
     }
 }
@@ -169,6 +170,21 @@ int geo_cutlinks_backward(const geo_mesh* mesh, const geo_level* lv, int64_t n_l
     if (n_links > 0 && (!link_cell || !link_dir || !link_tri || !grad_q || !grad_verts)) return GEO_ERR_ARG;
     return launch_backward(dev_mesh(mesh), dev_level(lv), n_links, link_cell, link_dir, link_tri, grad_q, grad_verts,
                            (hipStream_t)stream);
+}
+
+int geo_links_dense(const geo_level* lv, int64_t n_links, const int32_t* link_cell, const uint8_t* link_dir,
+                    const float* link_q, const int32_t* link_tri, int32_t lattice, int64_t cap, int32_t* block_map,
+                    float* dense_q, int32_t* dense_tri, int64_t* d_nbnd, void* ws, size_t ws_bytes,
+                    geo_stream_t stream) {
+    if (!check_level(lv) || n_links < 0 || cap < 0 || !d_nbnd) return GEO_ERR_ARG;
+    if (lattice != 19 && lattice != 27) return GEO_ERR_ARG;
+    if (n_links > 0 && (!link_cell || !link_dir || !link_q || !link_tri)) return GEO_ERR_ARG;
+    if (lv->nblocks > 0 && !block_map) return GEO_ERR_ARG;
+    if (cap > 0 && (!dense_q || !dense_tri)) return GEO_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(dense_q) | reinterpret_cast<uintptr_t>(dense_tri)) & 15) return GEO_ERR_ARG;
+    if (!ws && ws_bytes) return GEO_ERR_WORKSPACE;
+    return launch_links_dense(lv->nblocks, n_links, link_cell, link_dir, link_q, link_tri, lattice, cap, block_map,
+                              dense_q, dense_tri, d_nbnd, ws, ws_bytes, (hipStream_t)stream);
 }
 
 const char* geo_version(void) { return "libgeo 0.1 (gfx950)"; }

@@ -15,7 +15,7 @@ from dataclasses import dataclass, field
 import torch
 
 from . import (GEO_BINS_LINKS, GEO_BINS_ROWS, GEO_CALL_BINS_LINKS, GEO_CALL_BINS_ROWS, GEO_CALL_CUTLINKS,
-               GEO_CALL_REFINE, GEO_NSTATS, GEO_PREC_F32_FALLBACK, GEO_PREC_F64, geo_build_bins, geo_cutlinks,
+               GEO_CALL_LINKS_DENSE, GEO_CALL_REFINE, geo_links_dense, GEO_NSTATS, GEO_PREC_F32_FALLBACK, GEO_PREC_F64, geo_build_bins, geo_cutlinks,
                geo_cutlinks_backward, geo_level0_blocks, geo_nprop, geo_refine_flags, geo_voxelize,
                geo_workspace_size, make_bins, make_level, make_mesh)
 
@@ -197,6 +197,43 @@ class Embedder:
             L.cell, L.dir, L.q, L.tri = cell[:c], dr[:c], q[:c], tri[:c]
         checks.append((2 * lf + 2, cap, lkey, _apply))
         return L
+
+
+@dataclass
+class DenseLinks:
+    """Dense per-block layout of a link table: block_map [nb] (-1 or the
+    boundary-block index), q and tri [nbnd, Q, 64] (-1 where no link)."""
+    block_map: torch.Tensor
+    q: torch.Tensor
+    tri: torch.Tensor
+
+    @property
+    def nbnd(self) -> int:
+        return int(self.q.shape[0])
+
+
+def links_dense(emb: "Embedding", caps: dict = None) -> DenseLinks:
+    """The paper's dense link-length layout built from the table of emb."""
+    rec, L = emb.levels[-1], emb.links
+    dev = L.cell.device
+    nb = int(rec.bcoord.shape[0])
+    qd = 26 if emb.lattice == 27 else 18
+    lvd = make_level(emb.n0, emb.lf, rec.bcoord, [lv.child_map for lv in emb.levels[:-1]])
+    caps = {} if caps is None else caps
+    cap = caps.get("dense", max(64, nb // 4))
+    ws = torch.empty(geo_workspace_size(GEO_CALL_LINKS_DENSE, nb, 0), dtype=torch.uint8, device=dev)
+    block_map = torch.empty(max(nb, 1), dtype=torch.int32, device=dev)
+    d_n = torch.zeros(1, dtype=torch.int64, device=dev)
+    for _ in range(2):
+        q = torch.empty((cap, qd, 64), dtype=torch.float32, device=dev)
+        tri = torch.empty((cap, qd, 64), dtype=torch.int32, device=dev)
+        geo_links_dense(lvd, L.n, L.cell, L.dir, L.q, L.tri, emb.lattice, cap, block_map, q, tri, d_n, ws)
+        n = int(d_n.item())
+        if n <= cap:
+            caps["dense"] = cap
+            return DenseLinks(block_map[:nb], q[:n], tri[:n])
+        cap = n
+    raise RuntimeError("dense layout capacity did not converge")
 
 
 class _NoTimer:

@@ -80,3 +80,27 @@ def test_overflowed_buffers_are_redone():
         assert np.array_equal(np.sort(x.rows_val.cpu().numpy()), np.sort(y.rows_val.cpu().numpy()))
     for f in ("mask", "cell", "dir", "q", "tri"):
         assert np.array_equal(getattr(ref.links, f).cpu().numpy(), getattr(got.links, f).cpu().numpy()), f
+
+
+@pytest.mark.parametrize("name", ["star_small", "star_small_q27", "box_small"])
+def test_dense_layout(name):
+    """The paper's dense per-block layout, built on the GPU from the GPU table,
+    against the same layout built from the oracle's table."""
+    from paper_2512_01251_amd.pipeline import links_dense
+    w, ref = _ref(name)
+    say(f"[parity] dense layout {name}")
+    emb, _, _ = gpu_embed(w, "f32")
+    dn = links_dense(emb)
+    rl = ref["links"]
+    nb = len(ref["levels"][-1]["bcoord"])
+    od = oracle.links_dense(nb, rl["cell"], rl["dir"], rl["q"], rl["tri"], w.lattice)
+    assert np.array_equal(dn.block_map.cpu().numpy(), od["block_map"])
+    gq, gt = dn.q.cpu().numpy(), dn.tri.cpu().numpy()
+    assert gq.shape == od["q"].shape
+    assert np.array_equal(gq == -1, od["q"] == -1) and np.array_equal(gt == -1, od["tri"] == -1)
+    assert np.abs(gq - od["q"]).max() <= 1e-5
+    # hit triangles where the oracle's is unique
+    tied = oracle.links_dense(nb, rl["cell"], rl["dir"], rl["q"], rl["tied"].astype(np.int32), w.lattice)["tri"]
+    sel = tied == 0
+    assert np.array_equal(gt[sel], od["tri"][sel])
+    say(f"[parity] dense layout {name} ok: {dn.nbnd} boundary blocks of {nb}")

@@ -475,3 +475,39 @@ def test_gradient_matches_finite_differences(small):
                 assert abs(fd - g[vj, ax]) <= 1e-6 * max(1.0, np.abs(g[vj]).sum())
                 checked += 1
     assert checked > 150
+
+
+def test_dense_layout_fixture():
+    # two boundary blocks (1 and 3) of four, D3Q19: the layout written out by hand
+    ks = oracle.lattice_dirs(19)
+    assert len(ks) == 18 and 13 not in ks and 0 not in ks and 1 in ks and 26 not in ks
+    cell = np.array([64 * 1 + 5, 64 * 1 + 5, 64 * 3 + 63])
+    dirs = np.array([1, 14, 25], dtype=np.uint8)     # k = 1, 14 and 25 are directions 0, 9 and 17 of D3Q19
+    q = np.array([0.25, 0.5, 1.0])
+    tri = np.array([7, 8, 9])
+    d = oracle.links_dense(4, cell, dirs, q, tri, 19)
+    assert d["block_map"].tolist() == [-1, 0, -1, 1]
+    assert d["q"].shape == (2, 18, 64) and d["tri"].shape == (2, 18, 64)
+    exp_q = np.full((2, 18, 64), -1.0, np.float32)
+    exp_t = np.full((2, 18, 64), -1, np.int32)
+    exp_q[0, 0, 5], exp_t[0, 0, 5] = 0.25, 7
+    exp_q[0, 9, 5], exp_t[0, 9, 5] = 0.5, 8
+    exp_q[1, 17, 63], exp_t[1, 17, 63] = 1.0, 9
+    assert np.array_equal(d["q"], exp_q) and np.array_equal(d["tri"], exp_t)
+
+
+def test_dense_layout_round_trip():
+    # every link sits at its slot, and nothing else is set
+    w = configs.star_small(n_theta=14, n_phi=16, n0=32, lf=1)
+    ref = oracle.embed(w.mesh, w.n0, w.lf, 27, w.d_spec)
+    L, nb = ref["links"], len(ref["levels"][-1]["bcoord"])
+    d = oracle.links_dense(nb, L["cell"], L["dir"], L["q"], L["tri"], 27)
+    j, s, t = np.nonzero(d["tri"] >= 0)
+    blocks = np.nonzero(d["block_map"] >= 0)[0]
+    ks = oracle.lattice_dirs(27)
+    order = np.lexsort((ks[s], t, blocks[j]))
+    assert len(order) == L["n"]
+    assert np.array_equal((64 * blocks[j] + t)[order], L["cell"])
+    assert np.array_equal(ks[s][order], L["dir"])
+    assert np.array_equal(d["q"][j, s, t][order], L["q"].astype(np.float32))
+    assert (d["q"][d["tri"] < 0] == -1).all()
