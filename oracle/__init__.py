@@ -18,6 +18,9 @@ What each function follows (section names of the paper):
       the nearest surface crossing along the link, as a fraction of the link.
   grad -- derivative of q with respect to the hit triangle's vertices
       (closed form; not in the paper).
+  links_dense -- "Memory Allocations for Boundary Cells": the per-block layout.
+  bounce_back -- the linear interpolated bounce-back of Bouzidi et al. that
+      the link lengths serve (Related Work), and simple bounce-back.
 """
 from __future__ import annotations
 
@@ -267,6 +270,79 @@ def links_dense(nblocks: int, link_cell, link_dir, link_q, link_tri, lattice: in
     q[j, s, cell % 64] = np.asarray(link_q, dtype=np.float32)
     tri[j, s, cell % 64] = np.asarray(link_tri, dtype=np.int32)
     return {"block_map": block_map, "q": q, "tri": tri}
+
+
+def bounce_back(n0, L: int, bcoord, solid_cells, link_cell, link_dir, link_q, lattice: int, interpolate: bool,
+                f_post, f_new):
+    """Boundary step of a lattice Boltzmann solver at the links of a level
+    (Related Work: linear interpolated bounce-back of Bouzidi et al., which
+    needs the boundary node and one upstream fluid node per direction).
+
+    For the link of fluid node x in direction p with length fraction q and
+    the opposite direction pb (c_pb = -c_p), the population of x in direction
+    pb after streaming is
+      simple bounce-back:  f*_p(x)
+      q <  1/2:  f*_p interpolated linearly at x - (1 - 2q) c_p between x and
+                 the upstream node x - c_p:  2q f*_p(x) + (1 - 2q) f*_p(x - c_p)
+      q >= 1/2:  the reflected f*_p(x), now at x + (2q - 1) c_p, and f*_pb(x),
+                 at x - c_p after streaming, interpolated linearly at x:
+                 f*_p(x) / (2q) + (1 - 1/(2q)) f*_pb(x)
+    Where q < 1/2 and x - c_p is solid or in no block of the level, the one
+    fluid node that form needs is not there and the link takes simple
+    bounce-back (the q >= 1/2 form would extrapolate with a weight
+    1 - 1/(2q) that is unbounded as q -> 0).
+
+    Populations are [nblocks, Qf, 64] (directions in increasing k, rest
+    included), arithmetic in float64 on the given values; the q < 1/2
+    decision is taken on q as given (float32 in the table).  Returns
+    (f_new as float64 with the link entries replaced, number of links that
+    took the fallback)."""
+    dirs = sorted(set(lattice_dirs(lattice).tolist()) | {13})
+    slot = np.full(27, -1, np.int64)
+    slot[dirs] = np.arange(len(dirs))
+    out = np.array(f_new, dtype=np.float64, copy=True)
+    fpost = np.asarray(f_post, dtype=np.float64)
+    cell = np.asarray(link_cell, dtype=np.int64)
+    k = np.asarray(link_dir, dtype=np.int64)
+    qv = np.asarray(link_q)
+    if len(cell) == 0:
+        return out, 0
+    b, t = cell // 64, cell % 64
+    c = np.stack([k % 3 - 1, (k // 3) % 3 - 1, k // 9 - 1], axis=1)
+    # the opposite direction, found from its vector
+    cb = -c
+    kb = (cb[:, 0] + 1) + 3 * (cb[:, 1] + 1) + 9 * (cb[:, 2] + 1)
+    local = np.stack([t % 4, (t // 4) % 4, t // 16], axis=1)
+    x = 4 * np.asarray(bcoord, dtype=np.int64)[b] + local
+    fp = fpost[b, slot[k], t]
+    fb = fpost[b, slot[kb], t]
+    if not interpolate:
+        out[b, slot[kb], t] = fp
+        return out, 0
+    # upstream node x - c_p: its block (if the level has it) and its cell
+    u = x - c
+    ubc = u // 4
+    ncell = np.array([int(v) << L for v in n0], dtype=np.int64)
+    inside = np.all((u >= 0) & (u < ncell[None, :]), axis=1)
+    nbx = ncell // 4
+    key = lambda a: (a[:, 2] * nbx[1] + a[:, 1]) * nbx[0] + a[:, 0]
+    bkeys = key(np.asarray(bcoord, dtype=np.int64))
+    order = np.argsort(bkeys)
+    uk = key(ubc)
+    pos = np.clip(np.searchsorted(bkeys[order], uk), 0, len(order) - 1)
+    ub = order[pos]
+    exists = inside & (bkeys[ub] == uk)
+    ul = u - 4 * ubc
+    ut = ul[:, 0] + 4 * ul[:, 1] + 16 * ul[:, 2]
+    up_fluid = exists & (np.asarray(solid_cells)[ub, ut] == 0)
+    fu = fpost[ub, slot[k], ut]
+    q = qv.astype(np.float64)
+    near = qv < 0.5
+    use_up = near & up_fluid
+    v = np.where(near, np.where(use_up, 2.0 * q * fp + (1.0 - 2.0 * q) * fu, fp),
+                 fp / (2.0 * q) + (1.0 - 1.0 / (2.0 * q)) * fb)
+    out[b, slot[kb], t] = v
+    return out, int(np.count_nonzero(near & ~up_fluid))
 
 
 # ----------------------------------------------------------------------------

@@ -511,3 +511,176 @@ def test_dense_layout_round_trip():
     assert np.array_equal(ks[s][order], L["dir"])
     assert np.array_equal(d["q"][j, s, t][order], L["q"].astype(np.float32))
     assert (d["q"][d["tri"] < 0] == -1).all()
+
+
+# ----------------------------------------------------------------------------
+# bounce-back at the links: geometric construction, physical invariants
+# ----------------------------------------------------------------------------
+
+def _bb_level(lattice, seed=4):
+    """A level-1 forest of 16^3 cells with some blocks missing, random solid
+    cells, a random link table and noisy populations."""
+    from synth import populations
+    rng = np.random.default_rng(seed)
+    n0, L = (8, 8, 8), 1
+    allb = np.array([[x, y, z] for z in range(4) for y in range(4) for x in range(4)], dtype=np.int32)
+    keep = np.sort(rng.choice(len(allb), size=44, replace=False))
+    bcoord = allb[keep]
+    solid = (rng.uniform(size=(len(bcoord), 64)) < 0.25).astype(np.uint8)
+    links = populations.random_links(len(bcoord), lattice, seed + 1, per_block=30)
+    f_post = populations.populations(len(bcoord), lattice, seed + 2)
+    f_new = populations.populations(len(bcoord), lattice, seed + 3)
+    return n0, L, bcoord, solid, links, f_post, f_new
+
+
+def _pop_slot(lattice):
+    ks = [k for k in range(27) if lattice == 27 or (_dirs()[k] ** 2).sum() <= 2]
+    return {k: i for i, k in enumerate(ks)}
+
+
+def _reverse(k):
+    """The direction whose vector is -c_k, found by search."""
+    D = _dirs()
+    return int(np.nonzero(np.all(D == -D[k], axis=1))[0][0])
+
+
+def _brute_upstream(bcoord, solid, n0, L, b, t, k):
+    """(block, cell) of the node x - c_k if it is a fluid node of the level,
+    else None: a linear scan of the block list."""
+    c = _dirs()[k]
+    x = 4 * bcoord[b] + np.array([t % 4, (t // 4) % 4, t // 16])
+    u = x - c
+    if np.any(u < 0) or np.any(u >= np.array(n0) * 2 ** L):
+        return None
+    for j, bc in enumerate(bcoord):
+        if np.array_equal(bc, u // 4):
+            r = u - 4 * bc
+            ut = int(r[0] + 4 * r[1] + 16 * r[2])
+            return None if solid[j, ut] else (j, ut)
+    return None
+
+
+@pytest.mark.parametrize("lattice", [19, 27])
+def test_simple_bounce_back_reverses_the_population(lattice):
+    """Simple bounce-back: the population leaving x towards the wall comes
+    back to x with the reversed velocity; nothing else changes."""
+    n0, L, bc, solid, lk, fpost, fnew = _bb_level(lattice)
+    out, nfb = oracle.bounce_back(n0, L, bc, solid, lk["cell"], lk["dir"], lk["q"], lattice, False, fpost, fnew)
+    slot = _pop_slot(lattice)
+    expect = fnew.astype(np.float64).copy()
+    for cell, k in zip(lk["cell"], lk["dir"]):
+        b, t = divmod(int(cell), 64)
+        expect[b, slot[_reverse(int(k))], t] = fpost[b, slot[int(k)], t]
+    assert nfb == 0
+    assert np.array_equal(out, expect)
+
+
+@pytest.mark.parametrize("lattice", [19, 27])
+@pytest.mark.parametrize("interpolate", [False, True])
+def test_bounce_back_keeps_a_fluid_at_rest(lattice, interpolate):
+    """A fluid at rest at a wall at rest stays at rest: with f* = rho w_k
+    (rest equilibrium, w_k = w_-k) every returned population is rho w of its
+    direction, whatever q (the interpolation weights sum to one)."""
+    from synth import populations
+    n0, L, bc, solid, lk, _, fnew = _bb_level(lattice)
+    w = populations.lattice_weights(lattice)
+    rest = np.broadcast_to(1.3 * w[None, :, None], fnew.shape).astype(np.float64)
+    out, _ = oracle.bounce_back(n0, L, bc, solid, lk["cell"], lk["dir"], lk["q"], lattice, interpolate, rest, fnew)
+    slot = _pop_slot(lattice)
+    for cell, k in zip(lk["cell"], lk["dir"]):
+        b, t = divmod(int(cell), 64)
+        s = slot[_reverse(int(k))]
+        assert abs(out[b, s, t] - 1.3 * w[s]) <= 1e-15
+
+
+@pytest.mark.parametrize("lattice", [19, 27])
+def test_interpolated_bounce_back_geometric_construction(lattice):
+    """Linear interpolated bounce-back built from the particle paths, with the
+    upstream node found by a linear scan.  q < 1/2: the population that ends
+    at x after reflection started at x - (1 - 2q) c_p, between x - c_p and x
+    (values f*_p).  q >= 1/2: the reflected f*_p(x) ends at x + (2q - 1) c_p
+    and f*_pb(x) streams to x - c_p; the value at x lies on the line through
+    them.  q < 1/2 without an upstream fluid node: simple bounce-back.
+    Interpolation by np.interp."""
+    n0, L, bc, solid, lk, fpost, fnew = _bb_level(lattice)
+    out, nfb = oracle.bounce_back(n0, L, bc, solid, lk["cell"], lk["dir"], lk["q"], lattice, True, fpost, fnew)
+    slot = _pop_slot(lattice)
+    fb_count, near_up = 0, 0
+    for cell, k, q in zip(lk["cell"], lk["dir"], lk["q"]):
+        b, t = divmod(int(cell), 64)
+        k, q = int(k), float(q)
+        kb = _reverse(k)
+        fp = float(fpost[b, slot[k], t])
+        up = _brute_upstream(bc, solid, n0, L, b, t, k)
+        if q < 0.5 and up is not None:
+            near_up += 1
+            fu = float(fpost[up[0], slot[k], up[1]])
+            want = np.interp(-(1 - 2 * q), [-1.0, 0.0], [fu, fp])
+        elif q < 0.5:
+            fb_count += 1
+            want = fp
+        else:
+            fbv = float(fpost[b, slot[kb], t])
+            want = np.interp(0.0, [-1.0, 2 * q - 1], [fbv, fp])
+        assert abs(out[b, slot[kb], t] - want) <= 1e-15, (b, t, k, q)
+    assert nfb == fb_count
+    assert near_up > 100 and fb_count > 20  # both branches and the fallback are exercised
+
+
+def test_interpolated_bounce_back_special_fractions():
+    """Wall midway (q = 1/2): interpolated and simple bounce-back agree.
+    Wall on the solid node (q = 1): the mean of f*_p(x) and f*_pb(x).
+    Wall on the fluid node (q -> 0) with an upstream fluid node: f*_p(x - c_p)."""
+    lattice = 27
+    n0, L, bc, solid, lk, fpost, fnew = _bb_level(lattice, seed=9)
+    slot = _pop_slot(lattice)
+    q = lk["q"].copy()
+    n = len(q)
+    q[: n // 3] = 0.5
+    q[n // 3: 2 * n // 3] = 1.0
+    q[2 * n // 3:] = np.float32(2.0 ** -30)
+    ibb, _ = oracle.bounce_back(n0, L, bc, solid, lk["cell"], lk["dir"], q, lattice, True, fpost, fnew)
+    sbb, _ = oracle.bounce_back(n0, L, bc, solid, lk["cell"], lk["dir"], q, lattice, False, fpost, fnew)
+    checked = 0
+    for i, (cell, k) in enumerate(zip(lk["cell"], lk["dir"])):
+        b, t = divmod(int(cell), 64)
+        k = int(k)
+        s = slot[_reverse(k)]
+        if i < n // 3:
+            assert ibb[b, s, t] == sbb[b, s, t]
+        elif i < 2 * n // 3:
+            assert abs(ibb[b, s, t] - 0.5 * (float(fpost[b, slot[k], t]) + float(fpost[b, s, t]))) <= 1e-16
+        else:
+            up = _brute_upstream(bc, solid, n0, L, b, t, k)
+            if up is not None:
+                assert abs(ibb[b, s, t] - fpost[up[0], slot[k], up[1]]) <= 1e-9
+                checked += 1
+    assert checked > 50
+
+
+def test_interpolated_bounce_back_reproduces_linear_fields():
+    """Populations linear in position, f*_p(y) = a_p + g . y: where the
+    upstream node is fluid and q < 1/2 the result is the field's value at the
+    departure point x - (1 - 2q) c_p."""
+    lattice = 19
+    n0, L, bc, solid, lk, _, fnew = _bb_level(lattice, seed=12)
+    slot = _pop_slot(lattice)
+    rng = np.random.default_rng(3)
+    a = rng.uniform(0.1, 0.2, len(slot))
+    g = np.array([0.003, -0.002, 0.0015])
+    local = np.stack([np.arange(64) % 4, (np.arange(64) // 4) % 4, np.arange(64) // 16], axis=1)
+    y = 4 * bc[:, None, :].astype(np.float64) + local[None]
+    field = a[None, :, None] + (y @ g)[:, None, :]
+    out, _ = oracle.bounce_back(n0, L, bc, solid, lk["cell"], lk["dir"], lk["q"], lattice, True, field, fnew)
+    D = _dirs()
+    checked = 0
+    for cell, k, q in zip(lk["cell"], lk["dir"], lk["q"]):
+        b, t = divmod(int(cell), 64)
+        k, q = int(k), float(q)
+        if q >= 0.5 or _brute_upstream(bc, solid, n0, L, b, t, k) is None:
+            continue
+        x = 4 * bc[b] + local[t]
+        want = a[slot[k]] + g @ (x - (1 - 2 * q) * D[k])
+        assert abs(out[b, slot[_reverse(k)], t] - want) <= 1e-14
+        checked += 1
+    assert checked > 100
