@@ -167,6 +167,62 @@ def cpu_baseline(w, out, chunk_blocks=120000, min_seconds=10.0, max_chunks=16, w
     return res
 
 
+def bounce_back_bench(emb, dn, reps=20):
+    """Simple and linear interpolated bounce-back (Bouzidi) over the finest
+    level's links on synthetic float32 post-collision populations laid out
+    [nblocks][Qf][64], read from the dense layout dn.  Device time from the
+    library's kernel timer on the launching stream.  Algorithmic bytes: the
+    block map, the dense q of every boundary block, and per link the
+    populations read (one for simple, two for interpolated bounce-back) and
+    the one written.  For scale: one device copy of the whole population
+    array (the least traffic a full solver step on the level moves)."""
+    import torch
+    from paper_2512_01251_amd import (GEO_KT_IBB, geo_ibb, geo_kernel_timer, geo_kernel_timer_read,
+                                      make_level)
+    from synth.populations import lattice_weights
+    rec = emb.levels[-1]
+    nb = int(rec.bcoord.shape[0])
+    qf = 27 if emb.lattice == 27 else 19
+    dev = rec.bcoord.device
+    w = torch.tensor(lattice_weights(emb.lattice), dtype=torch.float32, device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(41)
+    f_post = torch.empty((nb, qf, 64), dtype=torch.float32, device=dev)
+    f_post.uniform_(0.9, 1.1, generator=g).mul_(w[None, :, None])
+    f_new = torch.zeros_like(f_post)
+    lvd = make_level(emb.n0, emb.lf, rec.bcoord, [lv.child_map for lv in emb.levels[:-1]])
+    d_fb = torch.zeros(1, dtype=torch.int64, device=dev)
+    res = {"blocks": nb, "boundary_blocks": dn.nbnd, "links": emb.links.n, "dtype": "f32",
+           "populations_gb": 2 * f_post.numel() * 4 / 1e9}
+    base = 4 * nb + dn.nbnd * dn.q.shape[1] * 64 * 4
+    for name, interp, per_link in (("sbb", False, 8), ("ibb", True, 12)):
+        geo_ibb(lvd, rec.solid, dn.block_map, dn.q, dn.nbnd, emb.lattice, interp, f_post, f_new, d_fb)
+        _sync()
+        geo_kernel_timer(GEO_KT_IBB, True)
+        for _ in range(reps):
+            geo_ibb(lvd, rec.solid, dn.block_map, dn.q, dn.nbnd, emb.lattice, interp, f_post, f_new)
+        ms, n = geo_kernel_timer_read(GEO_KT_IBB)
+        geo_kernel_timer(GEO_KT_IBB, False)
+        ms /= max(n, 1)
+        nbytes = base + per_link * emb.links.n
+        res[f"{name}_ms"] = ms
+        res[f"{name}_bytes"] = nbytes
+        res[f"{name}_gb_per_s"] = nbytes / (ms * 1e-3) / 1e9
+    res["fallback_links"] = int(d_fb.item())
+    res["ibb_over_sbb"] = res["ibb_ms"] / res["sbb_ms"]
+    s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f_new.copy_(f_post)
+    s_ev.record()
+    for _ in range(3):
+        f_new.copy_(f_post)
+    e_ev.record()
+    _sync()
+    res["population_copy_ms"] = s_ev.elapsed_time(e_ev) / 3
+    res["ibb_over_population_copy"] = res["ibb_ms"] / res["population_copy_ms"]
+    del f_post, f_new
+    return res
+
+
 def copy_probe(nbytes=1 << 30, reps=3):
     """A plain elementwise kernel of known traffic (reads nbytes, writes nbytes:
     y = -x over float32; nothing else here negates), for calibrating the HBM
@@ -190,6 +246,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-links", action="store_true", help="also time the oracle's q on a link sample")
     ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--no-bounce-back", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB device copy first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -282,6 +339,10 @@ def main():
     dbytes = dn.nbnd * qd * 64 * 8 + 4 * dn.block_map.numel() + 13 * n_links
     line["dense_layout"] = {"ms": dms, "boundary_blocks": dn.nbnd, "directions": qd, "bytes": dbytes,
                             "gb_per_s": dbytes / (dms * 1e-3) / 1e9}
+    if not args.no_bounce_back:
+        print("[bench] bounce-back on the finest level", file=sys.stderr, flush=True)
+        line["bounce_back"] = bounce_back_bench(out, dn)
+    del dn
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, out, with_links=args.cpu_links)

@@ -239,6 +239,36 @@ int geo_links_dense(const geo_level* lv, int64_t n_links, const int32_t* link_ce
                     geo_stream_t stream);
 
 /*
+ * Linear interpolated bounce-back of Bouzidi et al. (Related Work: the
+ * boundary condition the link lengths serve; it needs one fluid node besides
+ * the boundary node in each linked direction), applied on one level from the
+ * dense layout of geo_links_dense: the boundary step of a lattice Boltzmann
+ * solver.  The geometry is at rest.
+ *   f_post, f_new (device, dtype GEO_F32 or GEO_F64, [nblocks][Qf][64],
+ *     Qf = 19 or 27): post-collision and streamed populations;
+ *     f[(b * Qf + s) * 64 + t] is cell t of block b in the s-th direction of
+ *     the lattice, directions in increasing k with the rest direction
+ *     included.  They must not overlap.
+ *   For each link of cell x (cell t of block b) in direction p with length
+ *   fraction q (from dense_q), pb = 26 - p the opposite direction, the entry
+ *   of x in direction pb of f_new is set to
+ *     interpolate = 0:  f*_p(x)                                  (bounce-back)
+ *     q <  1/2:         2q f*_p(x) + (1 - 2q) f*_p(x - c_p)
+ *     q >= 1/2:         f*_p(x) / (2q) + (1 - 1/(2q)) f*_pb(x)
+ *   with f* = f_post, computed in the populations' type (the decision
+ *   q < 1/2 on the float32 q).  Where q < 1/2 and x - c_p is solid (solid
+ *   bits of geo_voxelize) or in no block of the level, the link takes simple
+ *   bounce-back, and *d_fallback (device uint64, optional, accumulated)
+ *   counts those links.  No other entry of f_new is written.
+ *   block_map, dense_q: from geo_links_dense on this level and lattice
+ *     (lattice 19 or 27); nbnd = boundary blocks that dense_q holds (blocks
+ *     mapped to an index >= nbnd are skipped).
+ */
+int geo_ibb(const geo_level* lv, const uint64_t* solid, const int32_t* block_map, const float* dense_q,
+            int64_t nbnd, int32_t lattice, int32_t interpolate, int32_t dtype, const void* f_post,
+            void* f_new, uint64_t* d_fallback, geo_stream_t stream);
+
+/*
  * Backward of q with respect to the vertices (not in the paper): for each
  * link i with hit triangle (v0, v1, v2), barycentrics lambda of the hit point
  * and normal n, grad_verts[v_j] += grad_q[i] * lambda_j * n / (n . h c_k)
@@ -270,7 +300,8 @@ enum {
     GEO_KT_VOXELIZE = 1,   /* solid voxelization of one level                   */
     GEO_KT_LINKS_BINS = 2, /* LINKS bins, triangle pass (block overlap tests)    */
     GEO_KT_CUTLINKS_Q = 3, /* cut-link q kernel (nearest hit per link)          */
-    GEO_KT_COUNT = 4
+    GEO_KT_IBB = 4,        /* interpolated / simple bounce-back kernel          */
+    GEO_KT_COUNT = 5
 };
 #define GEO_KT_MAX_LAUNCHES 4096
 int geo_kernel_timer(int32_t kernel, int32_t enable);

@@ -23,13 +23,13 @@ GEO_CALL_BINS_ROWS, GEO_CALL_BINS_LINKS, GEO_CALL_REFINE, GEO_CALL_CUTLINKS, GEO
 GEO_STAT_F32_TO_F64, GEO_STAT_EXACT, GEO_STAT_LINKS_EXACT, GEO_STAT_CONTRACT, GEO_STAT_STAGED, GEO_STAT_PAIRS = 0, 1, 2, 3, 4, 5
 GEO_STAT_TASKS = 6
 GEO_NSTATS = 7
-GEO_KT_ROWS, GEO_KT_VOXELIZE, GEO_KT_LINKS_BINS, GEO_KT_CUTLINKS_Q, GEO_KT_COUNT = 0, 1, 2, 3, 4
+GEO_KT_ROWS, GEO_KT_VOXELIZE, GEO_KT_LINKS_BINS, GEO_KT_CUTLINKS_Q, GEO_KT_IBB, GEO_KT_COUNT = 0, 1, 2, 3, 4, 5
 GEO_KT_MAX_LAUNCHES = 4096
 GEO_MAX_LEVELS = 12
 GEO_MAX_RES = 32767
 
 EXPORTS = ["geo_workspace_size", "geo_nprop", "geo_level0_blocks", "geo_build_bins", "geo_voxelize",
-           "geo_refine_flags", "geo_cutlinks", "geo_cutlinks_backward", "geo_links_dense", "geo_kernel_timer", "geo_kernel_timer_read", "geo_version"]
+           "geo_refine_flags", "geo_cutlinks", "geo_cutlinks_backward", "geo_links_dense", "geo_ibb", "geo_kernel_timer", "geo_kernel_timer_read", "geo_version"]
 
 
 class GeoError(RuntimeError):
@@ -74,6 +74,7 @@ def lib():
         L.geo_cutlinks.argtypes = [MP, LP, BP, BP, i32, i32, P, i64, P, P, P, P, P, P, P, sz, P]
         L.geo_cutlinks_backward.argtypes = [MP, LP, i64, P, P, P, P, P, P]
         L.geo_links_dense.argtypes = [LP, i64, P, P, P, P, i32, i64, P, P, P, P, P, sz, P]
+        L.geo_ibb.argtypes = [LP, P, P, P, i64, i32, i32, i32, P, P, P, P]
         L.geo_kernel_timer.argtypes = [i32, i32]
         L.geo_kernel_timer_read.argtypes = [i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.geo_version.restype = C.c_char_p
@@ -198,6 +199,17 @@ def geo_links_dense(level: geo_level, n_links: int, link_cell, link_dir, link_q,
                                _ptr(dense_tri), _ptr(d_nbnd), _ptr(ws), ws.numel() if ws is not None else 0,
                                _stream(stream))
     _check(rc, "geo_links_dense")
+
+
+def geo_ibb(level: geo_level, solid, block_map, dense_q, nbnd: int, lattice: int, interpolate: bool, f_post,
+            f_new, d_fallback=None, stream=None):
+    import torch
+    if f_post.dtype != f_new.dtype or f_post.dtype not in (torch.float32, torch.float64):
+        raise GeoError("geo_ibb: f_post and f_new must both be float32 or both float64")
+    dt = GEO_F64 if f_post.dtype == torch.float64 else GEO_F32
+    rc = lib().geo_ibb(C.byref(level), _ptr(solid), _ptr(block_map), _ptr(dense_q), int(nbnd), int(lattice),
+                       int(bool(interpolate)), dt, _ptr(f_post), _ptr(f_new), _ptr(d_fallback), _stream(stream))
+    _check(rc, "geo_ibb")
 
 
 def geo_cutlinks_backward(mesh: geo_mesh, level: geo_level, n_links: int, link_cell, link_dir,

@@ -278,6 +278,9 @@ size_t geo_dense_ws_bytes(int64_t nb);
 int launch_links_dense(int64_t nb, int64_t n_links, const int32_t* link_cell, const uint8_t* link_dir,
                        const float* link_q, const int32_t* link_tri, int lattice, int64_t cap, int32_t* block_map,
                        float* dense_q, int32_t* dense_tri, int64_t* d_nbnd, void* ws, size_t ws_bytes, hipStream_t s);
+int launch_ibb(const DevLevel& d, const uint64_t* solid, const int32_t* block_map, const float* dense_q,
+               int64_t nbnd, int lattice, int interpolate, int dtype, const void* f_post, void* f_new,
+               unsigned long long* d_fallback, hipStream_t s);
 int launch_voxelize(const DevLevel& d, const int32_t* off, const int32_t* val, int64_t cap,
                     uint64_t* solid, hipStream_t s);
 int launch_level0(const int32_t n0[3], int32_t* bcoord, hipStream_t s);

@@ -140,6 +140,53 @@ def test_star7m_sampled(c2, precision):
     assert st[3] == 0
 
 
+def test_star7m_bounce_back_properties(c2):
+    """Bounce-back over every link of the 7.2M-triangle star's finest level
+    (D3Q27), float32 populations for all its blocks, checked by properties
+    that hold at any size:
+      simple bounce-back returns f*_p(x) into the reversed direction of x,
+        for every link, and writes nothing else;
+      a fluid at rest (f* = w_k) stays at rest under interpolated
+        bounce-back: every returned population is exactly w of its direction
+        (fp = fu = fb makes every form exact)."""
+    import torch
+    from paper_2512_01251_amd import geo_ibb, make_level
+    from paper_2512_01251_amd.pipeline import links_dense
+    from synth.populations import lattice_weights
+    w = c2
+    say("[fullsize] star7m bounce-back")
+    emb, _, _ = gpu_embed(w, "f32")
+    dn = links_dense(emb)
+    rec = emb.levels[-1]
+    nb = int(rec.bcoord.shape[0])
+    lvd = make_level(emb.n0, emb.lf, rec.bcoord, [lv.child_map for lv in emb.levels[:-1]])
+    D = np.array([[k % 3 - 1, (k // 3) % 3 - 1, k // 9 - 1] for k in range(27)])
+    rev = torch.tensor([int(np.nonzero(np.all(D == -D[k], axis=1))[0][0]) for k in range(27)], device="cuda")
+    cell = emb.links.cell.long()
+    k = emb.links.dir.long()
+    b, t = cell // 64, cell % 64
+    src = (b * 27 + k) * 64 + t          # D3Q27: slot = k
+    dst = (b * 27 + rev[k]) * 64 + t
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    f_post = torch.empty((nb, 27, 64), dtype=torch.float32, device="cuda").uniform_(0.5, 1.0, generator=g)
+    f_new = torch.full_like(f_post, -1.0)
+    geo_ibb(lvd, rec.solid, dn.block_map, dn.q, dn.nbnd, 27, False, f_post, f_new)
+    torch.cuda.synchronize()
+    assert torch.equal(f_new.view(-1)[dst], f_post.view(-1)[src])
+    assert int((f_new != -1.0).sum().item()) == emb.links.n
+    wt = torch.tensor(lattice_weights(27), dtype=torch.float32, device="cuda")
+    f_post.copy_(wt[None, :, None].expand_as(f_post))
+    f_new.fill_(-1.0)
+    d_fb = torch.zeros(1, dtype=torch.int64, device="cuda")
+    geo_ibb(lvd, rec.solid, dn.block_map, dn.q, dn.nbnd, 27, True, f_post, f_new, d_fb)
+    torch.cuda.synchronize()
+    assert torch.equal(f_new.view(-1)[dst], wt[rev[k]])
+    assert int((f_new != -1.0).sum().item()) == emb.links.n
+    say(f"[fullsize] star7m bounce-back ok: {emb.links.n} links, {dn.nbnd} boundary blocks, "
+        f"{int(d_fb.item())} fallbacks")
+
+
 # ----------------------------------------------------------------------------
 # degenerate and multi-body workloads at full size (256^3 base, levels 0..3,
 # D3Q19): faces and vertices on cell-centre planes and lattice points, and 64

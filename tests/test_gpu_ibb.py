@@ -1,0 +1,130 @@
+"""Bounce-back at the cut links on the GPU (geo_ibb) against the oracle.
+
+Synthetic link tables on a real forest give both sides the same q, so the
+populations must agree to the rounding of the arithmetic type; the tables
+the path builds give each side its own q (agreeing within 1e-5), so the
+bound there includes the q difference times the slope of the formulas.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import configs, populations
+from gpu_helpers import gpu_embed, say
+
+pytestmark = pytest.mark.gpu
+
+WORKLOADS = {
+    "star_small": lambda: configs.star_small(),
+    "star_small_q27": lambda: configs.star_small(lattice=27),
+}
+_cache = {}
+
+
+def _setup(name):
+    if name not in _cache:
+        w = WORKLOADS[name]()
+        ref = oracle.embed(w.mesh, w.n0, w.lf, w.lattice, w.d_spec)
+        emb, _, _ = gpu_embed(w, "f32")
+        r = ref["levels"][-1]
+        g = emb.levels[-1]
+        assert np.array_equal(g.bcoord.cpu().numpy(), r["bcoord"])
+        assert np.array_equal(g.solid.cpu().numpy().view(np.uint64), r["solid"])
+        _cache[name] = (w, ref, emb)
+    return _cache[name]
+
+
+def _level(emb):
+    from paper_2512_01251_amd import make_level
+    rec = emb.levels[-1]
+    return make_level(emb.n0, emb.lf, rec.bcoord, [lv.child_map for lv in emb.levels[:-1]])
+
+
+def _gpu_bounce_back(emb, dense, lattice, interpolate, f_post, f_new):
+    import torch
+    from paper_2512_01251_amd import geo_ibb
+    out = f_new.clone()
+    d_fb = torch.zeros(1, dtype=torch.int64, device=out.device)
+    geo_ibb(_level(emb), emb.levels[-1].solid, dense.block_map, dense.q, dense.nbnd, lattice, interpolate,
+            f_post, out, d_fb)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64), int(d_fb.item())
+
+
+def _dense_from(emb, cell, dr, q):
+    """Dense layout of a given table, built by the library."""
+    import torch
+    from paper_2512_01251_amd.pipeline import Links, links_dense
+    dev = emb.levels[-1].bcoord.device
+    n = len(cell)
+    tab = Links(mask=None, cell=torch.from_numpy(cell).to(dev), dir=torch.from_numpy(dr).to(dev),
+                q=torch.from_numpy(q).to(dev), tri=torch.zeros(n, dtype=torch.int32, device=dev))
+    saved = emb.links
+    emb.links = tab
+    try:
+        return links_dense(emb)
+    finally:
+        emb.links = saved
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("interpolate", [True, False])
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_bounce_back_synthetic_table(name, interpolate, dtype):
+    import torch
+    w, ref, emb = _setup(name)
+    r = ref["levels"][-1]
+    nb = len(r["bcoord"])
+    say(f"[ibb] synthetic {name} interpolate={interpolate} {dtype}: {nb} blocks")
+    lk = populations.random_links(nb, w.lattice, seed=21, per_block=48)
+    npdt = np.float64 if dtype == "f64" else np.float32
+    fpost = populations.populations(nb, w.lattice, seed=22, dtype=npdt)
+    fnew = populations.populations(nb, w.lattice, seed=23, dtype=npdt)
+    dense = _dense_from(emb, lk["cell"], lk["dir"], lk["q"])
+    got, gfb = _gpu_bounce_back(emb, dense, w.lattice, interpolate, torch.from_numpy(fpost).cuda(),
+                                torch.from_numpy(fnew).cuda())
+    want, ofb = oracle.bounce_back(w.n0, w.lf, r["bcoord"], r["solid_cells"], lk["cell"], lk["dir"], lk["q"],
+                                   w.lattice, interpolate, fpost, fnew)
+    # entries without a link are left as they were
+    untouched = want == fnew.astype(np.float64)
+    assert np.array_equal(got[untouched], want[untouched])
+    eps = 2.0 ** -53 if dtype == "f64" else 2.0 ** -24
+    tol = 8 * eps * float(np.abs(fpost).max())
+    err = np.abs(got - want).max()
+    assert err <= tol, (err, tol)
+    assert gfb == ofb
+    if not interpolate:
+        assert np.array_equal(got, want)
+    changed = np.count_nonzero(got != fnew.astype(np.float64))
+    say(f"[ibb] synthetic {name} ok: {len(lk['cell'])} links, {gfb} fallbacks, {changed} changed, max err {err:.2e}")
+
+
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_bounce_back_on_the_cut_link_table(name):
+    """The path's own table and layout on the GPU, the oracle's table on the
+    CPU.  q agrees within 1e-5; v has slope at most 2 |f_p - f_u| in q below
+    1/2 and |f_p - f_b| / (2 q^2) <= 2 |f_p - f_b| above, and both forms (and
+    the fallback) give f*_p at q = 1/2, so v agrees within 4e-5 max|f| plus
+    rounding."""
+    import torch
+    from paper_2512_01251_amd.pipeline import links_dense
+    w, ref, emb = _setup(name)
+    r = ref["levels"][-1]
+    rl = ref["links"]
+    nb = len(r["bcoord"])
+    say(f"[ibb] table {name}: {rl['n']} links")
+    dense = links_dense(emb)
+    fpost = populations.populations(nb, w.lattice, seed=31)
+    fnew = populations.populations(nb, w.lattice, seed=32)
+    got, gfb = _gpu_bounce_back(emb, dense, w.lattice, True, torch.from_numpy(fpost).cuda(),
+                                torch.from_numpy(fnew).cuda())
+    q32 = rl["q"].astype(np.float32)
+    want, ofb = oracle.bounce_back(w.n0, w.lf, r["bcoord"], r["solid_cells"], rl["cell"], rl["dir"], q32,
+                                   w.lattice, True, fpost, fnew)
+    fmax = float(np.abs(fpost).max())
+    err = np.abs(got - want).max()
+    assert err <= 4e-5 * fmax + 8 * 2.0 ** -24 * fmax, err
+    # the fallback decision may differ only for q within 1e-5 of 1/2
+    near_half = int(np.count_nonzero(np.abs(rl["q"] - 0.5) <= 2e-5))
+    assert abs(gfb - ofb) <= near_half
+    say(f"[ibb] table {name} ok: {gfb} fallbacks (oracle {ofb}), max err {err:.2e}")
