@@ -21,6 +21,8 @@ What each function follows (section names of the paper):
   links_dense -- "Memory Allocations for Boundary Cells": the per-block layout.
   bounce_back -- the linear interpolated bounce-back of Bouzidi et al. that
       the link lengths serve (Related Work), and simple bounce-back.
+  solid_change -- cells whose solid flag a moving geometry changes
+      (Limitations and Future Work: uncovered nodes become fluid).
 """
 from __future__ import annotations
 
@@ -343,6 +345,22 @@ def bounce_back(n0, L: int, bcoord, solid_cells, link_cell, link_dir, link_q, la
                  fp / (2.0 * q) + (1.0 - 1.0 / (2.0 * q)) * fb)
     out[b, slot[kb], t] = v
     return out, int(np.count_nonzero(near & ~up_fluid))
+
+
+def solid_change(mesh_prev, n0, L: int, bcoord, solid_cells) -> dict:
+    """Cells of the blocks bcoord of level L whose solid flag differs between
+    the previous mesh and the current classification solid_cells ([nb, 64],
+    1 = solid): spawned = solid before and fluid now (nodes the geometry
+    uncovered, which a solver must initialise), covered = fluid before and
+    solid now.  The previous mesh is evaluated at the current cell centres by
+    the same point rule as every solid flag.  Returns [nb, 64] uint8 masks and
+    their counts."""
+    before = classify_blocks(mesh_prev, n0, L, bcoord).astype(bool)
+    now = np.asarray(solid_cells).astype(bool)
+    spawned = before & ~now
+    covered = now & ~before
+    return {"spawned": spawned.astype(np.uint8), "covered": covered.astype(np.uint8),
+            "n_spawned": int(spawned.sum()), "n_covered": int(covered.sum())}
 
 
 # ----------------------------------------------------------------------------

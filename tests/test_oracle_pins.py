@@ -684,3 +684,74 @@ def test_interpolated_bounce_back_reproduces_linear_fields():
         assert abs(out[b, slot[_reverse(k)], t] - want) <= 1e-14
         checked += 1
     assert checked > 100
+
+
+# ----------------------------------------------------------------------------
+# moving geometry: solid changes
+# ----------------------------------------------------------------------------
+
+def _translated(mesh, d):
+    return meshes.Mesh(mesh.verts + np.asarray(d, dtype=mesh.verts.dtype), mesh.tris.copy())
+
+
+def test_solid_change_of_a_translated_convex_body(ico):
+    """Convex icosphere moved by a sub-cell offset: a centre was uncovered iff
+    it satisfies every face half-space of the old position and not of the new
+    one (and the reverse for covered), on a level whose blocks the new
+    geometry's forest does not have to share."""
+    w, r = ico
+    d = np.array([0.37, -0.21, 0.13])
+    moved = _translated(w.mesh, d)
+    bc = r["levels"][0]["bcoord"]
+    now = oracle.classify_blocks(moved, w.n0, 0, bc)
+    ch = oracle.solid_change(w.mesh, w.n0, 0, bc, now)
+    P = _centres(bc, 0)
+
+    def inside(V):
+        T = w.mesh.tris
+        a = V[T[:, 0]]
+        n = np.cross(V[T[:, 1]] - a, V[T[:, 2]] - a)
+        ok = np.ones(len(P), bool)
+        for f in range(len(T)):
+            g = (a[f] - P) @ n[f]
+            assert np.abs(g).min() > 1e-9
+            ok &= g >= 0
+        return ok
+
+    old, new = inside(w.mesh.verts), inside(moved.verts)
+    assert np.array_equal(ch["spawned"].reshape(-1).astype(bool), old & ~new)
+    assert np.array_equal(ch["covered"].reshape(-1).astype(bool), new & ~old)
+    assert ch["n_spawned"] > 100 and ch["n_covered"] > 100
+
+
+def test_solid_change_of_a_whole_cell_shift():
+    """A shift by exactly one cell along x moves every solid flag one cell:
+    solid_now(i) = solid_before(i - 1).  So the uncovered cells are those
+    solid before whose -x neighbour was fluid, computed here from the
+    unshifted classification alone; no motion changes nothing."""
+    w = configs.star_small(lf=1)
+    n0, L = w.n0, 0
+    nb = (n0[0] // 4) * (n0[1] // 4) * (n0[2] // 4)
+    bc = oracle.level0_blocks(n0)
+    before = oracle.classify_blocks(w.mesh, n0, L, bc)
+    moved = _translated(w.mesh, [1.0, 0.0, 0.0])
+    now = oracle.classify_blocks(moved, n0, L, bc)
+    ch = oracle.solid_change(w.mesh, n0, L, bc, now)
+    # dense grid of the level-0 flags, x fastest
+    grid = np.zeros((n0[2], n0[1], n0[0]), bool)
+    t = np.arange(64)
+    for b in range(nb):
+        x0, y0, z0 = 4 * bc[b]
+        grid[z0 + t // 16, y0 + (t // 4) % 4, x0 + t % 4] = before[b].astype(bool)
+    shifted = np.zeros_like(grid)
+    shifted[:, :, 1:] = grid[:, :, :-1]
+    sp, cv = np.zeros_like(grid), np.zeros_like(grid)
+    for b in range(nb):
+        x0, y0, z0 = 4 * bc[b]
+        sp[z0 + t // 16, y0 + (t // 4) % 4, x0 + t % 4] = ch["spawned"][b].astype(bool)
+        cv[z0 + t // 16, y0 + (t // 4) % 4, x0 + t % 4] = ch["covered"][b].astype(bool)
+    assert np.array_equal(sp, grid & ~shifted)
+    assert np.array_equal(cv, shifted & ~grid)
+    assert sp.sum() > 50
+    still = oracle.solid_change(w.mesh, n0, L, bc, before)
+    assert still["n_spawned"] == 0 and still["n_covered"] == 0
