@@ -223,6 +223,58 @@ def bounce_back_bench(emb, dn, reps=20):
     return res
 
 
+def moving_bench(emb, V, T, w, steps=6):
+    """A shape-sensitivity loop over a moving geometry: each step moves the
+    vertices (a rotation by 0.002 rad per step about z through the centre and
+    a shift of (0.031, -0.017, 0.023) cells), rebuilds the whole embedding
+    with the same Embedder, forms L = sum q with the vertex gradient
+    (backward of q), and finds the cells of the finest level that the motion
+    uncovered or covered.  Wall-clock per step and the device time of each
+    part (events on the current stream)."""
+    import torch
+    from paper_2512_01251_amd import pipeline
+    c = V.double().mean(0)
+    d = torch.tensor([0.031, -0.017, 0.023], dtype=torch.float64, device=V.device)
+
+    def moved(s):
+        a = 0.002 * s
+        R = torch.tensor([[math.cos(a), -math.sin(a), 0.0], [math.sin(a), math.cos(a), 0.0], [0.0, 0.0, 1.0]],
+                         dtype=torch.float64, device=V.device)
+        return ((V.double() - c) @ R.T + c + s * d).to(V.dtype)
+
+    prev = None
+    parts = {"embed": 0.0, "backward": 0.0, "change": 0.0}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    counts = []
+    _sync()
+    t0 = time.perf_counter()
+    for s in range(steps + 1):
+        if s == 1:  # the first step (no previous geometry) is the warm-up
+            _sync()
+            t0 = time.perf_counter()
+            parts = {k: 0.0 for k in parts}
+        Vs = moved(s).requires_grad_(True)
+        ev[0].record()
+        out = emb.embed(Vs.detach(), T, w.n0, w.lf, w.lattice, w.d_spec, "f32", True)
+        ev[1].record()
+        q = pipeline.cut_link_q(Vs, T, out)
+        q.sum().backward()
+        ev[2].record()
+        ch = pipeline.solid_change(prev, out) if prev is not None else None
+        ev[3].record()
+        _sync()
+        parts["embed"] += ev[0].elapsed_time(ev[1])
+        parts["backward"] += ev[1].elapsed_time(ev[2])
+        parts["change"] += ev[2].elapsed_time(ev[3])
+        if ch is not None:
+            counts.append(ch.counts.cpu().tolist())
+        prev = out
+    _sync()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    return {"steps": steps, "ms_per_step": ms, "device_ms_per_step": {k: v / steps for k, v in parts.items()},
+            "links": out.links.n, "uncovered_covered_per_step": counts}
+
+
 def copy_probe(nbytes=1 << 30, reps=3):
     """A plain elementwise kernel of known traffic (reads nbytes, writes nbytes:
     y = -x over float32; nothing else here negates), for calibrating the HBM
@@ -247,6 +299,7 @@ def main():
     ap.add_argument("--cpu-links", action="store_true", help="also time the oracle's q on a link sample")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-bounce-back", action="store_true")
+    ap.add_argument("--no-moving", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB device copy first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -339,6 +392,9 @@ def main():
     dbytes = dn.nbnd * qd * 64 * 8 + 4 * dn.block_map.numel() + 13 * n_links
     line["dense_layout"] = {"ms": dms, "boundary_blocks": dn.nbnd, "directions": qd, "bytes": dbytes,
                             "gb_per_s": dbytes / (dms * 1e-3) / 1e9}
+    if not args.no_moving:
+        print("[bench] moving geometry loop", file=sys.stderr, flush=True)
+        line["moving_geometry"] = moving_bench(emb, V, T, w)
     if not args.no_bounce_back:
         print("[bench] bounce-back on the finest level", file=sys.stderr, flush=True)
         line["bounce_back"] = bounce_back_bench(out, dn)

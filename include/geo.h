@@ -269,6 +269,22 @@ int geo_ibb(const geo_level* lv, const uint64_t* solid, const int32_t* block_map
             void* f_new, uint64_t* d_fallback, geo_stream_t stream);
 
 /*
+ * Solid-flag changes of moving geometry (Limitations and Future Work: when the
+ * geometry moves, nodes it no longer covers become fluid and need an initial
+ * state).  prev, cur (device uint64[nblocks]): two classifications of the same
+ * blocks, bit t = cell t solid -- e.g. geo_voxelize of one level with the
+ * ROWS bins of the previous and of the current mesh (ROWS bins depend on the
+ * level only, not on its blocks, so a previous mesh's bins classify the
+ * current forest).  Writes, where the pointer is not NULL,
+ *   spawned[b] = prev[b] & ~cur[b]  (solid before, fluid now),
+ *   covered[b] = cur[b] & ~prev[b]  (fluid before, solid now),
+ * and adds their bit counts to d_counts[0] and d_counts[1] (device int64[2],
+ * accumulated; required).  Output arrays may alias neither input.
+ */
+int geo_solid_change(int64_t nblocks, const uint64_t* prev, const uint64_t* cur, uint64_t* spawned,
+                     uint64_t* covered, int64_t* d_counts, geo_stream_t stream);
+
+/*
  * Backward of q with respect to the vertices (not in the paper): for each
  * link i with hit triangle (v0, v1, v2), barycentrics lambda of the hit point
  * and normal n, grad_verts[v_j] += grad_q[i] * lambda_j * n / (n . h c_k)

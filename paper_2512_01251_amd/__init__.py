@@ -29,7 +29,7 @@ GEO_MAX_LEVELS = 12
 GEO_MAX_RES = 32767
 
 EXPORTS = ["geo_workspace_size", "geo_nprop", "geo_level0_blocks", "geo_build_bins", "geo_voxelize",
-           "geo_refine_flags", "geo_cutlinks", "geo_cutlinks_backward", "geo_links_dense", "geo_ibb", "geo_kernel_timer", "geo_kernel_timer_read", "geo_version"]
+           "geo_refine_flags", "geo_cutlinks", "geo_cutlinks_backward", "geo_links_dense", "geo_ibb", "geo_solid_change", "geo_kernel_timer", "geo_kernel_timer_read", "geo_version"]
 
 
 class GeoError(RuntimeError):
@@ -75,6 +75,7 @@ def lib():
         L.geo_cutlinks_backward.argtypes = [MP, LP, i64, P, P, P, P, P, P]
         L.geo_links_dense.argtypes = [LP, i64, P, P, P, P, i32, i64, P, P, P, P, P, sz, P]
         L.geo_ibb.argtypes = [LP, P, P, P, i64, i32, i32, i32, P, P, P, P]
+        L.geo_solid_change.argtypes = [i64, P, P, P, P, P, P]
         L.geo_kernel_timer.argtypes = [i32, i32]
         L.geo_kernel_timer_read.argtypes = [i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.geo_version.restype = C.c_char_p
@@ -210,6 +211,12 @@ def geo_ibb(level: geo_level, solid, block_map, dense_q, nbnd: int, lattice: int
     rc = lib().geo_ibb(C.byref(level), _ptr(solid), _ptr(block_map), _ptr(dense_q), int(nbnd), int(lattice),
                        int(bool(interpolate)), dt, _ptr(f_post), _ptr(f_new), _ptr(d_fallback), _stream(stream))
     _check(rc, "geo_ibb")
+
+
+def geo_solid_change(nblocks: int, prev, cur, spawned, covered, d_counts, stream=None):
+    rc = lib().geo_solid_change(int(nblocks), _ptr(prev), _ptr(cur), _ptr(spawned), _ptr(covered), _ptr(d_counts),
+                                _stream(stream))
+    _check(rc, "geo_solid_change")
 
 
 def geo_cutlinks_backward(mesh: geo_mesh, level: geo_level, n_links: int, link_cell, link_dir,

@@ -205,6 +205,14 @@ int geo_ibb(const geo_level* lv, const uint64_t* solid, const int32_t* block_map
                       reinterpret_cast<unsigned long long*>(d_fallback), (hipStream_t)stream);
 }
 
+int geo_solid_change(int64_t nblocks, const uint64_t* prev, const uint64_t* cur, uint64_t* spawned,
+                     uint64_t* covered, int64_t* d_counts, geo_stream_t stream) {
+    if (nblocks < 0 || !d_counts) return GEO_ERR_ARG;
+    if (nblocks > 0 && (!prev || !cur)) return GEO_ERR_ARG;
+    return launch_solid_change(nblocks, prev, cur, spawned, covered, reinterpret_cast<unsigned long long*>(d_counts),
+                               (hipStream_t)stream);
+}
+
 const char* geo_version(void) { return "libgeo 0.1 (gfx950)"; }
 
 }  // extern "C"

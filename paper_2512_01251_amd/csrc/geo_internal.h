@@ -281,6 +281,8 @@ int launch_links_dense(int64_t nb, int64_t n_links, const int32_t* link_cell, co
 int launch_ibb(const DevLevel& d, const uint64_t* solid, const int32_t* block_map, const float* dense_q,
                int64_t nbnd, int lattice, int interpolate, int dtype, const void* f_post, void* f_new,
                unsigned long long* d_fallback, hipStream_t s);
+int launch_solid_change(int64_t n, const uint64_t* prev, const uint64_t* cur, uint64_t* spawned, uint64_t* covered,
+                        unsigned long long* d_counts, hipStream_t s);
 int launch_voxelize(const DevLevel& d, const int32_t* off, const int32_t* val, int64_t cap,
                     uint64_t* solid, hipStream_t s);
 int launch_level0(const int32_t n0[3], int32_t* bcoord, hipStream_t s);

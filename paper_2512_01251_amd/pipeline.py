@@ -15,9 +15,10 @@ from dataclasses import dataclass, field
 import torch
 
 from . import (GEO_BINS_LINKS, GEO_BINS_ROWS, GEO_CALL_BINS_LINKS, GEO_CALL_BINS_ROWS, GEO_CALL_CUTLINKS,
-               GEO_CALL_LINKS_DENSE, GEO_CALL_REFINE, geo_links_dense, GEO_NSTATS, GEO_PREC_F32_FALLBACK, GEO_PREC_F64, geo_build_bins, geo_cutlinks,
-               geo_cutlinks_backward, geo_level0_blocks, geo_nprop, geo_refine_flags, geo_voxelize,
-               geo_workspace_size, make_bins, make_level, make_mesh)
+               GEO_CALL_LINKS_DENSE, GEO_CALL_REFINE, GEO_NSTATS, GEO_PREC_F32_FALLBACK, GEO_PREC_F64,
+               geo_build_bins, geo_cutlinks, geo_cutlinks_backward, geo_level0_blocks, geo_links_dense, geo_nprop,
+               geo_refine_flags, geo_solid_change, geo_voxelize, geo_workspace_size, make_bins, make_level,
+               make_mesh)
 
 PRECISIONS = {"f64": GEO_PREC_F64, "f32": GEO_PREC_F32_FALLBACK}
 
@@ -298,3 +299,57 @@ class CutLinkQ(torch.autograd.Function):
 def cut_link_q(verts, tris, emb: Embedding):
     child_maps = [lv.child_map for lv in emb.levels[:-1]]
     return CutLinkQ.apply(verts, tris, emb, child_maps)
+
+
+# ----------------------------------------------------------------------------
+# moving geometry: per-step rebuild, solid changes, gradient
+# ----------------------------------------------------------------------------
+
+@dataclass
+class SolidChange:
+    """Cells of one level whose solid flag changed since the previous
+    geometry: bit t of spawned[b] (covered[b]) is set iff cell t of block b
+    was solid (fluid) under the previous mesh and is fluid (solid) now;
+    counts = [spawned, covered] on the device."""
+    level: int
+    spawned: torch.Tensor
+    covered: torch.Tensor
+    counts: torch.Tensor
+
+
+def solid_change(prev: Embedding, emb: Embedding, level: int = None) -> SolidChange:
+    """Solid changes on one level (default: the finest) of emb against the
+    geometry that prev embedded on the same grid.  The previous mesh
+    classifies the current forest through its ROWS bins of that level, which
+    depend on the level and not on its blocks.  No host wait."""
+    L = emb.lf if level is None else level
+    if tuple(prev.n0) != tuple(emb.n0) or L >= len(prev.levels):
+        raise ValueError("solid_change needs two embeddings of the same grid and level")
+    rec, old = emb.levels[L], prev.levels[L]
+    dev = rec.bcoord.device
+    nb = int(rec.bcoord.shape[0])
+    lvd = make_level(emb.n0, L, rec.bcoord, [lv.child_map for lv in emb.levels[:L]])
+    nkeys = (emb.n0[1] << L) * (emb.n0[2] << L)
+    n_old = int(old.rows_val.numel())
+    d_cnt = torch.full((1,), n_old, dtype=torch.int64, device=dev)
+    rows = make_bins(GEO_BINS_ROWS, nkeys, old.rows_off, old.rows_val, n_old, d_cnt)
+    before = torch.empty(nb, dtype=torch.int64, device=dev)
+    geo_voxelize(lvd, rows, before)
+    spawned = torch.empty(nb, dtype=torch.int64, device=dev)
+    covered = torch.empty(nb, dtype=torch.int64, device=dev)
+    counts = torch.zeros(2, dtype=torch.int64, device=dev)
+    geo_solid_change(nb, before, rec.solid, spawned, covered, counts)
+    return SolidChange(L, spawned, covered, counts)
+
+
+def shape_step(embedder: Embedder, verts: torch.Tensor, tris: torch.Tensor, n0, lf: int, lattice: int,
+               d_spec: float = 2.0, precision: str = "f32", prev: Embedding = None):
+    """One step of a shape-sensitivity loop over a moving geometry: rebuild
+    the embedding for the current vertices (every level re-binned), the
+    cut-link lengths q as a differentiable function of the vertices, and the
+    solid changes of the finest level against the previous step's embedding
+    (None on the first step).  Returns (emb, q, change)."""
+    emb = embedder.embed(verts.detach(), tris, n0, lf, lattice, d_spec, precision, True)
+    q = cut_link_q(verts, tris, emb)
+    change = solid_change(prev, emb) if prev is not None else None
+    return emb, q, change

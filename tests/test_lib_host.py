@@ -253,3 +253,12 @@ def test_bounce_back_arguments_are_checked_on_the_host(geo):
     # missing solid bits
     assert L.geo_ibb(C.byref(lv), None, p, p, 1, 27, 1, geo.GEO_F32, p, p + 8 * 27 * 64 * 4, None,
                      None) == geo.GEO_ERR_ARG
+
+
+def test_solid_change_arguments_are_checked_on_the_host(geo):
+    L = geo.lib()
+    cnt = (C.c_int64 * 2)()
+    assert L.geo_solid_change(0, None, None, None, None, C.addressof(cnt), None) == geo.GEO_OK
+    assert L.geo_solid_change(0, None, None, None, None, None, None) == geo.GEO_ERR_ARG
+    assert L.geo_solid_change(-1, None, None, None, None, C.addressof(cnt), None) == geo.GEO_ERR_ARG
+    assert L.geo_solid_change(4, None, None, None, None, C.addressof(cnt), None) == geo.GEO_ERR_ARG
