@@ -23,6 +23,9 @@ What each function follows (section names of the paper):
       the link lengths serve (Related Work), and simple bounce-back.
   solid_change -- cells whose solid flag a moving geometry changes
       (Limitations and Future Work: uncovered nodes become fluid).
+  embed2d and the *2d functions -- the quadtree form the paper says the
+      method covers (4x4 blocks, four children, D2Q9), on polygons given by
+      edges (embed2d.c).
 """
 from __future__ import annotations
 
@@ -35,7 +38,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "liboracle.so")
-_SRC = [os.path.join(_HERE, f) for f in ("exact.c", "embed.c")]
+_SRC = [os.path.join(_HERE, f) for f in ("exact.c", "embed.c", "embed2d.c")]
 _lib = None
 
 
@@ -74,6 +77,12 @@ def lib():
         L.or_q_points.argtypes = [P, P, i32, P, i32, i64, P, P, P, P, P]
         L.or_grad.argtypes = [P, P, i32, P, i32, i64, P, i64, P, P, P, P, P]
         L.or_num_threads.restype = i32
+        L.or2_solid_point.argtypes = [P, P, P, i32, P]
+        L.or2_classify_blocks.argtypes = [P, P, i32, P, i32, i64, P, i32, P]
+        L.or2_refine.argtypes = [P, i32, i64, P, P, i32, P, P, P, P]
+        L.or2_refine.restype = i64
+        L.or2_links.argtypes = [P, P, i32, P, i32, i64, P, i64, P, P, P, P, P, P]
+        L.or2_links.restype = i64
         _lib = L
     return _lib
 
@@ -384,4 +393,97 @@ def embed(mesh, n0, lf: int, lattice: int, d_spec: float = 2.0, with_links: bool
     out = {"levels": levels, "n_prop": npr}
     if with_links:
         out["links"] = links(mesh, n0, lf, levels[-1]["bcoord"], lattice)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# 2D: quadtrees of 4x4 blocks on polygons (vertices [nv, 2], edges [ne, 2])
+# ----------------------------------------------------------------------------
+
+def _poly_arrays(poly):
+    V = np.ascontiguousarray(poly.verts, dtype=np.float64)
+    E = np.ascontiguousarray(poly.edges, dtype=np.int32)
+    return V, E
+
+
+def level0_blocks2d(n0) -> np.ndarray:
+    """All level-0 blocks of a 2D grid, bx fastest."""
+    nbx, nby = n0[0] // 4, n0[1] // 4
+    y, x = np.meshgrid(np.arange(nby), np.arange(nbx), indexing="ij")
+    return np.stack([x.ravel(), y.ravel()], axis=1).astype(np.int32)
+
+
+def solid_point2d(poly, p) -> int:
+    """Point rule for one point, every edge a candidate."""
+    V, E = _poly_arrays(poly)
+    cand = np.arange(len(E), dtype=np.int32)
+    pt = np.ascontiguousarray(p, dtype=np.float64)
+    return int(lib().or2_solid_point(_p(V), _p(E), _p(cand), len(E), _p(pt)))
+
+
+def classify_blocks2d(poly, n0, L: int, bcoord, halo: bool = False) -> np.ndarray:
+    V, E = _poly_arrays(poly)
+    bc = np.ascontiguousarray(bcoord, dtype=np.int32)
+    w = 36 if halo else 16
+    out = np.zeros((len(bc), w), dtype=np.uint8)
+    n0a = np.ascontiguousarray(n0, dtype=np.int32)
+    lib().or2_classify_blocks(_p(V), _p(E), len(E), _p(n0a), L, len(bc), _p(bc), 1 if halo else 0, _p(out))
+    return out
+
+
+def pack_bits16(solid_cells: np.ndarray) -> np.ndarray:
+    """[nb, 16] -> [nb] uint16 with bit t = cell t."""
+    w = (1 << np.arange(16, dtype=np.uint32)).astype(np.uint32)
+    return (np.asarray(solid_cells, dtype=np.uint32) * w).sum(axis=1).astype(np.uint16)
+
+
+def refine2d(n0, L: int, bcoord, solid_cells, nprop: int) -> dict:
+    bc = np.ascontiguousarray(bcoord, dtype=np.int32)
+    nb = len(bc)
+    s = np.ascontiguousarray(solid_cells, dtype=np.uint8)
+    bclass = np.zeros(nb, np.uint8)
+    ref = np.zeros(nb, np.uint8)
+    cmap = np.zeros(nb, np.int32)
+    child = np.zeros((4 * nb, 2), np.int32)
+    n0a = np.ascontiguousarray(n0, dtype=np.int32)
+    nch = lib().or2_refine(_p(n0a), L, nb, _p(bc), _p(s), int(nprop), _p(bclass), _p(ref), _p(cmap), _p(child))
+    return {"bclass": bclass, "refine": ref, "child_map": cmap, "children": child[:nch].copy()}
+
+
+def links2d(poly, n0, L: int, bcoord) -> dict:
+    V, E = _poly_arrays(poly)
+    bc = np.ascontiguousarray(bcoord, dtype=np.int32)
+    nb = len(bc)
+    n0a = np.ascontiguousarray(n0, dtype=np.int32)
+    mask = np.zeros(nb * 16, np.uint16)
+    cap = 0
+    n = lib().or2_links(_p(V), _p(E), len(E), _p(n0a), L, nb, _p(bc), cap, _p(mask), None, None, None, None, None)
+    cell = np.zeros(max(n, 1), np.int32)
+    dr = np.zeros(max(n, 1), np.uint8)
+    q = np.zeros(max(n, 1), np.float64)
+    edge = np.zeros(max(n, 1), np.int32)
+    tied = np.zeros(max(n, 1), np.uint8)
+    lib().or2_links(_p(V), _p(E), len(E), _p(n0a), L, nb, _p(bc), n, _p(mask), _p(cell), _p(dr), _p(q), _p(edge),
+                    _p(tied))
+    return {"n": int(n), "mask": mask, "cell": cell[:n], "dir": dr[:n], "q": q[:n], "tri": edge[:n],
+            "tied": tied[:n]}
+
+
+def embed2d(poly, n0, lf: int, d_spec: float = 2.0, with_links: bool = True) -> dict:
+    """Level-by-level classification and refinement of a 2D grid (levels
+    0..lf), then the D2Q9 cut-link table on level lf."""
+    npr = n_prop(d_spec)
+    bcoord = level0_blocks2d(n0)
+    levels = []
+    for L in range(lf + 1):
+        cells = classify_blocks2d(poly, n0, L, bcoord)
+        rec = {"level": L, "bcoord": bcoord, "solid_cells": cells, "solid": pack_bits16(cells)}
+        if L < lf:
+            r = refine2d(n0, L, bcoord, cells, npr)
+            rec.update(r)
+            bcoord = r["children"]
+        levels.append(rec)
+    out = {"levels": levels, "n_prop": npr}
+    if with_links:
+        out["links"] = links2d(poly, n0, lf, levels[-1]["bcoord"])
     return out

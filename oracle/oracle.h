@@ -35,4 +35,14 @@ int or_segment_hit(const double* a, const double* b, const double* c,
 int or_hit_cmp(const or_hit* p, const or_hit* q);
 double or_hit_value(const or_hit* h);
 
+/* 2D form (embed2d.c) */
+int or2_solid_point(const double* V, const int32_t* E, const int32_t* cand, int n, const double* p);
+void or2_classify_blocks(const double* V, const int32_t* E, int ne, const int32_t* n0, int L, int64_t nb,
+                         const int32_t* bcoord, int halo, uint8_t* out);
+int64_t or2_refine(const int32_t* n0, int L, int64_t nb, const int32_t* bcoord, const uint8_t* solid, int n_prop,
+                   uint8_t* bclass, uint8_t* refine, int32_t* child_map, int32_t* child_bcoord);
+int64_t or2_links(const double* V, const int32_t* E, int ne, const int32_t* n0, int L, int64_t nb,
+                  const int32_t* bcoord, int64_t cap, uint16_t* mask_out, int32_t* link_cell, uint8_t* link_dir,
+                  double* link_q, int32_t* link_edge, uint8_t* link_tied);
+
 #endif

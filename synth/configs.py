@@ -11,7 +11,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import meshes
+from . import meshes, polygons
 
 
 @dataclass
@@ -96,6 +96,52 @@ def spheres_small(lf=2) -> Workload:
     return Workload("spheres8", m, (64, 64, 64), lf, 19)
 
 
+# ----------------------------------------------------------------------------
+# 2D (quadtrees, D2Q9): the paper's cylinder and square cases (root grid
+# 512^2, D_s = N_x / 64 base cells, the square 2 D_s wide and shifted by 0.7
+# base cells along x) and reduced versions for the oracle
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Workload2D:
+    name: str
+    poly: polygons.Polygon
+    n0: tuple
+    lf: int
+    d_spec: float = 2.0
+    lattice: int = 9
+
+
+def cylinder2d(lf=4, n_edges=4096) -> Workload2D:
+    """Circle of diameter 8 base cells (D_s = 1/64 of the unit domain) in the
+    centre of a 512^2 root grid; levels 0..lf (the paper's L_max = lf + 1)."""
+    return Workload2D("cylinder2d", polygons.circle(n_edges, (256.0, 256.0), 4.0), (512, 512), lf)
+
+
+def square2d(lf=4) -> Workload2D:
+    """Square of side 16 base cells (2 D_s) centred in a 512^2 root grid and
+    shifted by 0.7 base cells along +x."""
+    return Workload2D("square2d", polygons.rectangle((248.7, 248.0), (264.7, 264.0)), (512, 512), lf)
+
+
+def cylinder2d_small(lf=2) -> Workload2D:
+    return Workload2D("cylinder2d_small", polygons.circle(256, (32.3, 31.7), 10.0, noise=0.05, seed=3), (64, 64), lf)
+
+
+def square2d_small(lf=2) -> Workload2D:
+    """Edges on level-0 centre lines (x, y = k + 1/2): centres exactly on edges
+    and corners."""
+    return Workload2D("square2d_small", polygons.rectangle((20.5, 24.5), (40.5, 36.5)), (64, 64), lf)
+
+
+def shapes2d_small(lf=3) -> Workload2D:
+    """A non-convex star, a noisy circle and a small rectangle, disjoint."""
+    poly = polygons.union(polygons.star(7, (20.2, 40.3), 12.0, 5.0),
+                          polygons.circle(96, (46.1, 20.4), 8.0, noise=0.1, seed=5),
+                          polygons.rectangle((44.25, 44.5), (52.75, 50.125)))
+    return Workload2D("shapes2d_small", poly, (64, 64), lf)
+
+
 REGISTRY = {
     "icosphere64": icosphere64,
     "star112k": star112k,
@@ -107,6 +153,11 @@ REGISTRY = {
     "box_small": box_small,
     "prism_small": prism_small,
     "spheres_small": spheres_small,
+    "cylinder2d": cylinder2d,
+    "square2d": square2d,
+    "cylinder2d_small": cylinder2d_small,
+    "square2d_small": square2d_small,
+    "shapes2d_small": shapes2d_small,
 }
 
 
