@@ -101,20 +101,32 @@ def q_kernel_units(out):
     return int((nl * nc).sum()), int((nce * nc).sum())
 
 
+def q_kernel_source_hash() -> str:
+    """sha256 of the q kernel's source: its .hip file and the device code of
+    the shared header (the header's host-side launcher declarations, which
+    other entry points extend, are left out)."""
+    h = hashlib.sha256()
+    for p in Q_KERNEL_SOURCES:
+        text = open(p, "rb").read()
+        if p.endswith(".h"):
+            cut = text.find(b"// host-side launchers")
+            text = text if cut < 0 else text[:cut]
+        h.update(text)
+    return h.hexdigest()
+
+
 def q_kernel_traffic():
     """HBM bytes per launch of the q kernel from the committed counter profile,
     or None when the kernel's sources changed since the counters were taken."""
     if not os.path.exists(PMC_PROFILE):
         return None, "no counter profile"
-    h = hashlib.sha256()
-    for p in Q_KERNEL_SOURCES:
-        h.update(open(p, "rb").read())
+    digest = q_kernel_source_hash()
     fields = {}
     for line in open(PMC_PROFILE):
         if ":" in line:
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    if fields.get("source_sha256") != h.hexdigest():
+    if fields.get("source_sha256") != digest:
         return None, "kernel changed since the counters were taken"
     return float(fields["traffic_bytes_per_launch"]), "FETCH_SIZE + WRITE_SIZE, copy-calibrated"
 
@@ -275,6 +287,33 @@ def moving_bench(emb, V, T, w, steps=6):
             "links": out.links.n, "uncovered_covered_per_step": counts}
 
 
+def bench_2d(names=("cylinder2d", "square2d"), steps=20):
+    """The paper's 2D workloads (512^2 root grid, levels 0..4, D2Q9): wall time
+    of a whole 2D step (every level and the link table) with one Embedder2D,
+    after a warm-up step."""
+    import torch
+    from synth import configs
+    from paper_2512_01251_amd.pipeline2d import Embedder2D
+    out = {}
+    for name in names:
+        w = configs.get(name)
+        V = torch.from_numpy(np.ascontiguousarray(w.poly.verts, dtype=np.float64)).cuda()
+        E = torch.from_numpy(np.ascontiguousarray(w.poly.edges, dtype=np.int32)).cuda()
+        e = Embedder2D()
+        emb = e.embed(V, E, w.n0, w.lf, w.d_spec)
+        _sync()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            emb = e.embed(V, E, w.n0, w.lf, w.d_spec)
+        _sync()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        cells = sum(16 * int(lv.bcoord.shape[0]) for lv in emb.levels)
+        out[name] = {"ms_per_step": ms, "edges": int(E.shape[0]), "levels": w.lf + 1, "cells": cells,
+                     "links": emb.links.n, "blocks_per_level": [int(lv.bcoord.shape[0]) for lv in emb.levels],
+                     "mcells_per_s": cells / (ms * 1e-3) / 1e6}
+    return out
+
+
 def copy_probe(nbytes=1 << 30, reps=3):
     """A plain elementwise kernel of known traffic (reads nbytes, writes nbytes:
     y = -x over float32; nothing else here negates), for calibrating the HBM
@@ -300,6 +339,7 @@ def main():
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-bounce-back", action="store_true")
     ap.add_argument("--no-moving", action="store_true")
+    ap.add_argument("--no-2d", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB device copy first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -392,6 +432,9 @@ def main():
     dbytes = dn.nbnd * qd * 64 * 8 + 4 * dn.block_map.numel() + 13 * n_links
     line["dense_layout"] = {"ms": dms, "boundary_blocks": dn.nbnd, "directions": qd, "bytes": dbytes,
                             "gb_per_s": dbytes / (dms * 1e-3) / 1e9}
+    if not args.no_2d:
+        print("[bench] 2D workloads", file=sys.stderr, flush=True)
+        line["two_d"] = bench_2d()
     if not args.no_moving:
         print("[bench] moving geometry loop", file=sys.stderr, flush=True)
         line["moving_geometry"] = moving_bench(emb, V, T, w)

@@ -69,7 +69,10 @@ enum {
     GEO_CALL_BINS_LINKS = 1,
     GEO_CALL_REFINE = 2,
     GEO_CALL_CUTLINKS = 3,
-    GEO_CALL_LINKS_DENSE = 4 /* nkeys = blocks of the level, cap ignored */
+    GEO_CALL_LINKS_DENSE = 4, /* nkeys = blocks of the level, cap ignored */
+    GEO_CALL2_BINS = 5,       /* 2D bins: nkeys = row lines (ROWS) or blocks (LINKS) */
+    GEO_CALL2_REFINE = 6,     /* 2D refinement: nkeys = blocks                       */
+    GEO_CALL2_CUTLINKS = 7    /* 2D cut links: nkeys = blocks                        */
 };
 
 /* device statistics counters (uint64 each) */
@@ -267,6 +270,74 @@ int geo_links_dense(const geo_level* lv, int64_t n_links, const int32_t* link_ce
 int geo_ibb(const geo_level* lv, const uint64_t* solid, const int32_t* block_map, const float* dense_q,
             int64_t nbnd, int32_t lattice, int32_t interpolate, int32_t dtype, const void* f_post,
             void* f_new, uint64_t* d_fallback, geo_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * 2D: quadtrees (the paper's discussion of octrees holds for quadtrees in
+ * 2D).  Blocks of 4x4 cells, t = I + 4J; level 0 is all (n0x/4)(n0y/4)
+ * blocks, bx fastest; the children of a refined block follow in parent order,
+ * o = ox + 2 oy.  The geometry is a set of closed polygons given as edges,
+ * vertices double in base-cell units within [1/4, n0] (or 0); zero-length
+ * edges are ignored.  A cell is solid iff its centre lies in the closed
+ * region: on an edge, or with odd parity of the edges that the +x ray from
+ * it crosses, the ray lifted to height y + eps (so a horizontal edge is never
+ * crossed and a vertex on the ray counts once).  The lattice is D2Q9,
+ * k = (cx+1) + 3 (cy+1), 4 the rest direction.  Refinement follows the rules
+ * of geo_refine_flags over the 8-neighbourhood.  All integer outputs are
+ * exact; q is the first crossing, |error| <= 1e-5.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t nv;            /* vertices                               */
+    int32_t ne;            /* edges                                  */
+    const double* verts;   /* device [nv][2]                         */
+    const int32_t* edges;  /* device [ne][2] vertex indices          */
+} geo2_mesh;
+
+typedef struct {
+    int32_t n0[2];                        /* base cells per axis, multiples of 4 */
+    int32_t level;
+    int32_t nblocks;
+    const int32_t* bcoord;                /* device [nblocks][2]                 */
+    const int32_t* child[GEO_MAX_LEVELS]; /* device child maps of levels < L     */
+} geo2_level;
+
+/* Fill bcoord[(n0x/4)(n0y/4)][2] with the level-0 blocks, bx fastest. */
+int geo2_level0_blocks(const int32_t n0[2], int32_t* bcoord, geo_stream_t stream);
+
+/* Bins (Spatial Binning).  ROWS: one key per row line j of the level
+ * (ny = n0y 2^L keys), the edges whose closed y range holds the line's
+ * centre height.  LINKS: one key per block of the level, the edges that meet
+ * the block box grown by half a cell on every side (the appendix's 2D
+ * line-AABB case; a conservative test, which may add edges that never hit).
+ * Order within a key is unspecified; every consumer is order-independent.
+ * *bins->d_count = entries needed; entries beyond bins->cap are not written.
+ * Workspace: geo_workspace_size(GEO_CALL2_BINS, nkeys, 0). */
+int geo2_build_bins(const geo2_mesh* mesh, const geo2_level* lv, int32_t kind, geo_bins* bins, void* ws,
+                    size_t ws_bytes, geo_stream_t stream);
+
+/* Solid voxelization of one level: solid[b] bit t (device uint16[nblocks]). */
+int geo2_voxelize(const geo2_mesh* mesh, const geo2_level* lv, const geo_bins* rows, uint16_t* solid,
+                  geo_stream_t stream);
+
+/* Refinement flags of one level (Refinement Flagging and Propagation, Eq. 3,
+ * over the 8-neighbourhood); bclass, refine, child_map as for
+ * geo_refine_flags, child_bcoord[4 * refined][2], *d_nchild (device int64).
+ * Workspace: geo_workspace_size(GEO_CALL2_REFINE, nblocks, 0). */
+int geo2_refine_flags(const geo2_level* lv, const uint16_t* solid, int32_t n_prop, uint8_t* bclass,
+                      uint8_t* refine, int32_t* child_map, int32_t* child_bcoord, int64_t* d_nchild, void* ws,
+                      size_t ws_bytes, geo_stream_t stream);
+
+/* Cut links of one level (Boundary Cell Identification, Link-Length
+ * Computation) for D2Q9: fluid cell x, direction k, same-level centre
+ * x + h c_k solid (classified from the ROWS bins, also where its block does
+ * not exist; centres outside the domain are fluid).  Table order (block, t,
+ * k): link_cell = 16 b + t, link_dir = k, link_q = first crossing as a
+ * fraction of the link, link_edge = the crossed edge (the smallest index
+ * among edges crossed at the same double-precision parameter).
+ * *d_nlinks (device int64) = number of links; entries >= cap are not written.
+ * Workspace: geo_workspace_size(GEO_CALL2_CUTLINKS, nblocks, 0). */
+int geo2_cutlinks(const geo2_mesh* mesh, const geo2_level* lv, const geo_bins* rows, const geo_bins* links,
+                  int64_t cap, int64_t* d_nlinks, int32_t* link_cell, uint8_t* link_dir, float* link_q,
+                  int32_t* link_edge, void* ws, size_t ws_bytes, geo_stream_t stream);
 
 /*
  * Solid-flag changes of moving geometry (Limitations and Future Work: when the

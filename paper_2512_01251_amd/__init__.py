@@ -20,6 +20,7 @@ GEO_F32, GEO_F64 = 0, 1
 GEO_PREC_F64, GEO_PREC_F32_FALLBACK = 0, 1
 GEO_BINS_ROWS, GEO_BINS_LINKS = 0, 1
 GEO_CALL_BINS_ROWS, GEO_CALL_BINS_LINKS, GEO_CALL_REFINE, GEO_CALL_CUTLINKS, GEO_CALL_LINKS_DENSE = 0, 1, 2, 3, 4
+GEO_CALL2_BINS, GEO_CALL2_REFINE, GEO_CALL2_CUTLINKS = 5, 6, 7
 GEO_STAT_F32_TO_F64, GEO_STAT_EXACT, GEO_STAT_LINKS_EXACT, GEO_STAT_CONTRACT, GEO_STAT_STAGED, GEO_STAT_PAIRS = 0, 1, 2, 3, 4, 5
 GEO_STAT_TASKS = 6
 GEO_NSTATS = 7
@@ -29,7 +30,8 @@ GEO_MAX_LEVELS = 12
 GEO_MAX_RES = 32767
 
 EXPORTS = ["geo_workspace_size", "geo_nprop", "geo_level0_blocks", "geo_build_bins", "geo_voxelize",
-           "geo_refine_flags", "geo_cutlinks", "geo_cutlinks_backward", "geo_links_dense", "geo_ibb", "geo_solid_change", "geo_kernel_timer", "geo_kernel_timer_read", "geo_version"]
+           "geo_refine_flags", "geo_cutlinks", "geo_cutlinks_backward", "geo_links_dense", "geo_ibb", "geo_solid_change", "geo2_level0_blocks", "geo2_build_bins",
+           "geo2_voxelize", "geo2_refine_flags", "geo2_cutlinks", "geo_kernel_timer", "geo_kernel_timer_read", "geo_version"]
 
 
 class GeoError(RuntimeError):
@@ -43,6 +45,15 @@ class geo_mesh(C.Structure):
 
 class geo_level(C.Structure):
     _fields_ = [("n0", C.c_int32 * 3), ("level", C.c_int32), ("nblocks", C.c_int32),
+                ("bcoord", C.c_void_p), ("child", C.c_void_p * GEO_MAX_LEVELS)]
+
+
+class geo2_mesh(C.Structure):
+    _fields_ = [("nv", C.c_int32), ("ne", C.c_int32), ("verts", C.c_void_p), ("edges", C.c_void_p)]
+
+
+class geo2_level(C.Structure):
+    _fields_ = [("n0", C.c_int32 * 2), ("level", C.c_int32), ("nblocks", C.c_int32),
                 ("bcoord", C.c_void_p), ("child", C.c_void_p * GEO_MAX_LEVELS)]
 
 
@@ -76,6 +87,12 @@ def lib():
         L.geo_links_dense.argtypes = [LP, i64, P, P, P, P, i32, i64, P, P, P, P, P, sz, P]
         L.geo_ibb.argtypes = [LP, P, P, P, i64, i32, i32, i32, P, P, P, P]
         L.geo_solid_change.argtypes = [i64, P, P, P, P, P, P]
+        M2, L2 = C.POINTER(geo2_mesh), C.POINTER(geo2_level)
+        L.geo2_level0_blocks.argtypes = [P, P, P]
+        L.geo2_build_bins.argtypes = [M2, L2, i32, BP, P, sz, P]
+        L.geo2_voxelize.argtypes = [M2, L2, BP, P, P]
+        L.geo2_refine_flags.argtypes = [L2, P, i32, P, P, P, P, P, P, sz, P]
+        L.geo2_cutlinks.argtypes = [M2, L2, BP, BP, i64, P, P, P, P, P, P, sz, P]
         L.geo_kernel_timer.argtypes = [i32, i32]
         L.geo_kernel_timer_read.argtypes = [i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.geo_version.restype = C.c_char_p
@@ -116,6 +133,25 @@ def make_mesh(verts, tris) -> geo_mesh:
 def make_level(n0, level: int, bcoord, child_maps) -> geo_level:
     lv = geo_level()
     for a in range(3):
+        lv.n0[a] = int(n0[a])
+    lv.level = level
+    lv.nblocks = int(bcoord.shape[0])
+    lv.bcoord = bcoord.data_ptr() if bcoord.numel() else None
+    for l in range(level):
+        lv.child[l] = child_maps[l].data_ptr()
+    return lv
+
+
+def make_mesh2(verts, edges) -> geo2_mesh:
+    import torch
+    assert verts.is_cuda and edges.is_cuda and verts.is_contiguous() and edges.is_contiguous()
+    assert verts.dtype == torch.float64 and edges.dtype == torch.int32
+    return geo2_mesh(verts.shape[0], edges.shape[0], verts.data_ptr(), edges.data_ptr())
+
+
+def make_level2(n0, level: int, bcoord, child_maps) -> geo2_level:
+    lv = geo2_level()
+    for a in range(2):
         lv.n0[a] = int(n0[a])
     lv.level = level
     lv.nblocks = int(bcoord.shape[0])
@@ -217,6 +253,35 @@ def geo_solid_change(nblocks: int, prev, cur, spawned, covered, d_counts, stream
     rc = lib().geo_solid_change(int(nblocks), _ptr(prev), _ptr(cur), _ptr(spawned), _ptr(covered), _ptr(d_counts),
                                 _stream(stream))
     _check(rc, "geo_solid_change")
+
+
+def geo2_level0_blocks(n0, bcoord, stream=None):
+    arr = (C.c_int32 * 2)(*[int(x) for x in n0])
+    _check(lib().geo2_level0_blocks(arr, _ptr(bcoord), _stream(stream)), "geo2_level0_blocks")
+
+
+def geo2_build_bins(mesh: geo2_mesh, level: geo2_level, kind: int, bins: geo_bins, ws, stream=None):
+    _check(lib().geo2_build_bins(C.byref(mesh), C.byref(level), int(kind), C.byref(bins), _ptr(ws),
+                                 ws.numel() if ws is not None else 0, _stream(stream)), "geo2_build_bins")
+
+
+def geo2_voxelize(mesh: geo2_mesh, level: geo2_level, rows: geo_bins, solid, stream=None):
+    _check(lib().geo2_voxelize(C.byref(mesh), C.byref(level), C.byref(rows), _ptr(solid), _stream(stream)),
+           "geo2_voxelize")
+
+
+def geo2_refine_flags(level: geo2_level, solid, n_prop: int, bclass, refine, child_map, child_bcoord, d_nchild, ws,
+                      stream=None):
+    _check(lib().geo2_refine_flags(C.byref(level), _ptr(solid), int(n_prop), _ptr(bclass), _ptr(refine),
+                                   _ptr(child_map), _ptr(child_bcoord), _ptr(d_nchild), _ptr(ws),
+                                   ws.numel() if ws is not None else 0, _stream(stream)), "geo2_refine_flags")
+
+
+def geo2_cutlinks(mesh: geo2_mesh, level: geo2_level, rows: geo_bins, links: geo_bins, cap: int, d_nlinks,
+                  link_cell, link_dir, link_q, link_edge, ws, stream=None):
+    _check(lib().geo2_cutlinks(C.byref(mesh), C.byref(level), C.byref(rows), C.byref(links), int(cap),
+                               _ptr(d_nlinks), _ptr(link_cell), _ptr(link_dir), _ptr(link_q), _ptr(link_edge),
+                               _ptr(ws), ws.numel() if ws is not None else 0, _stream(stream)), "geo2_cutlinks")
 
 
 def geo_cutlinks_backward(mesh: geo_mesh, level: geo_level, n_links: int, link_cell, link_dir,

@@ -66,6 +66,9 @@ size_t geo_workspace_size(int32_t call, int64_t nkeys, int64_t cap) {
         case GEO_CALL_REFINE: return geo_refine_ws_bytes(nkeys);
         case GEO_CALL_CUTLINKS: return geo_cutlinks_ws_bytes(nkeys, cap);
         case GEO_CALL_LINKS_DENSE: return geo_dense_ws_bytes(nkeys);
+        case GEO_CALL2_BINS: return geo2_bins_ws_bytes(nkeys);
+        case GEO_CALL2_REFINE: return geo2_refine_ws_bytes(nkeys);
+        case GEO_CALL2_CUTLINKS: return geo2_cutlinks_ws_bytes(nkeys);
         default: return 0;
     }
 }

@@ -283,6 +283,9 @@ int launch_ibb(const DevLevel& d, const uint64_t* solid, const int32_t* block_ma
                unsigned long long* d_fallback, hipStream_t s);
 int launch_solid_change(int64_t n, const uint64_t* prev, const uint64_t* cur, uint64_t* spawned, uint64_t* covered,
                         unsigned long long* d_counts, hipStream_t s);
+size_t geo2_bins_ws_bytes(int64_t nkeys);
+size_t geo2_refine_ws_bytes(int64_t nb);
+size_t geo2_cutlinks_ws_bytes(int64_t nb);
 int launch_voxelize(const DevLevel& d, const int32_t* off, const int32_t* val, int64_t cap,
                     uint64_t* solid, hipStream_t s);
 int launch_level0(const int32_t n0[3], int32_t* bcoord, hipStream_t s);

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _header_functions():
     txt = open(os.path.join(ROOT, "include", "geo.h")).read()
-    return sorted(set(re.findall(r"^\w[\w\s\*]*?\b(geo_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\w[\w\s\*]*?\b(geo2?_\w+)\s*\(", txt, re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -262,3 +262,23 @@ def test_solid_change_arguments_are_checked_on_the_host(geo):
     assert L.geo_solid_change(0, None, None, None, None, None, None) == geo.GEO_ERR_ARG
     assert L.geo_solid_change(-1, None, None, None, None, C.addressof(cnt), None) == geo.GEO_ERR_ARG
     assert L.geo_solid_change(4, None, None, None, None, C.addressof(cnt), None) == geo.GEO_ERR_ARG
+
+
+def test_2d_arguments_are_checked_on_the_host(geo):
+    L = geo.lib()
+    n0 = (C.c_int32 * 2)(30, 32)
+    assert L.geo2_level0_blocks(n0, None, None) == geo.GEO_ERR_ARG
+    lv = geo.geo2_level()
+    lv.n0[0], lv.n0[1] = 32, 30         # not a multiple of 4
+    lv.level, lv.nblocks = 0, 0
+    mesh = geo.geo2_mesh(0, 0, None, None)
+    bins = geo.geo_bins(geo.GEO_BINS_ROWS, 0, None, None, 0, None)
+    assert L.geo2_build_bins(C.byref(mesh), C.byref(lv), geo.GEO_BINS_ROWS, C.byref(bins), None, 0,
+                             None) == geo.GEO_ERR_ARG
+    lv.n0[1] = 32
+    lv.level = 11                       # 32 * 2^11 > GEO_MAX_RES
+    assert L.geo2_voxelize(C.byref(mesh), C.byref(lv), C.byref(bins), None, None) == geo.GEO_ERR_ARG
+    lv.level = 0
+    assert L.geo2_refine_flags(C.byref(lv), None, 0, None, None, None, None, None, None, 0,
+                               None) == geo.GEO_ERR_ARG
+    assert geo.geo_workspace_size(geo.GEO_CALL2_REFINE, 100, 0) > 8 * 4 * 100
