@@ -9,10 +9,18 @@
 #define GEO_WAVE 64
 #define GEO_HD __host__ __device__
 
-GEO_HD __forceinline__ double geo_fabs(double x) { return x < 0 ? -x : x; }
-GEO_HD __forceinline__ float geo_fabs(float x) { return x < 0 ? -x : x; }
+// |x| and max/min of floating-point values through the builtins: on the GPU
+// |x| is a free source modifier and max/min one instruction each, where a
+// compare-and-select costs two (they differ only for -0 and NaN, which no
+// bound or decision here depends on)
+GEO_HD __forceinline__ double geo_fabs(double x) { return __builtin_fabs(x); }
+GEO_HD __forceinline__ float geo_fabs(float x) { return __builtin_fabsf(x); }
 template <typename R> GEO_HD __forceinline__ R geo_max(R a, R b) { return a > b ? a : b; }
 template <typename R> GEO_HD __forceinline__ R geo_min(R a, R b) { return a < b ? a : b; }
+GEO_HD __forceinline__ float geo_max(float a, float b) { return __builtin_fmaxf(a, b); }
+GEO_HD __forceinline__ float geo_min(float a, float b) { return __builtin_fminf(a, b); }
+GEO_HD __forceinline__ double geo_max(double a, double b) { return __builtin_fmax(a, b); }
+GEO_HD __forceinline__ double geo_min(double a, double b) { return __builtin_fmin(a, b); }
 // element k of (a0, a1, a2) as a value select, so that arrays stay in registers
 // (a select over loads from one array would be folded into a dynamic index)
 template <typename R> GEO_HD __forceinline__ R pick3(R a0, R a1, R a2, int k) {
