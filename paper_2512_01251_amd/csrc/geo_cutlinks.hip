@@ -573,12 +573,7 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
         if (b != b_prev) {  // uniform
             const uint32_t mk = block_link_mask(d, roff, rval, rcap, dirs, b, halo);
             smask[lane] = mk;
-            int c = __popc(mk), incl = c;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int tt = __shfl_up(incl, o, 64);
-                if (lane >= o) incl += tt;
-            }
+            const int c = __popc(mk), incl = wave_incl_scan(c);
             spre[lane] = incl - c;
             if (lane == 63) spre[64] = incl;
             b_prev = b;
@@ -674,12 +669,7 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
             // flatten up to CL_MAXC pairs per link over the wave
             const int pc = __popcll(pm);
             const int cnt = pc < CL_MAXC ? pc : CL_MAXC;
-            int inc2 = cnt;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int tt = __shfl_up(inc2, o, 64);
-                if (lane >= o) inc2 += tt;
-            }
+            const int inc2 = wave_incl_scan(cnt);
             const int pbase = inc2 - cnt;
             for (int j = 0; j < cnt; j++) {
                 const int slot = __ffsll(pm) - 1;

@@ -251,6 +251,20 @@ GEO_HD __forceinline__ int orient3d_filter(const R* a, const R* b, const R* c, c
     return det > bound ? 1 : (det < -bound ? -1 : 0);
 }
 
+// inclusive prefix sum over the 64 lanes of a wave (all lanes active), by
+// data-parallel primitives: shifts by 1, 2, 4, 8 within each row of 16 lanes,
+// then the last lane of rows 0 and 2 added to rows 1 and 3, and lane 31 to
+// rows 2 and 3.  No LDS round trip, unlike a shuffle-based scan.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
 // statistics: one atomic per wave for a per-lane count
 __device__ __forceinline__ void wave_count(uint64_t* ctr, unsigned n) {
     if (!ctr) return;

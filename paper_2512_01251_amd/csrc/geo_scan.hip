@@ -7,18 +7,8 @@ constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
 
-// inclusive scan across the 64 lanes of a wave
-__device__ __forceinline__ int wave_incl_scan(int v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int t = __shfl_up(v, o, 64);
-        if (lane >= o) v += t;
-    }
-    return v;
-}
-
-// exclusive scan across the block; returns the block total in *total
+// exclusive scan across the block (every thread calls it; the wave scan is
+// the shared data-parallel one); returns the block total in *total
 __device__ __forceinline__ int block_excl_scan(int v, int* total) {
     __shared__ int wsum[SCAN_THREADS / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
