@@ -154,6 +154,24 @@ __global__ void __launch_bounds__(64) k_cl_mask(DevLevel d, const int32_t* off, 
 // ------------------------------------------------------------------------
 enum { C_SLOW = 2 };
 
+// The float64 plane used for hit parameters: a copy for the float32 form,
+// the candidate's own plane for the float64 form (no second copy in LDS).
+template <typename R>
+struct PlaneF64 {
+    double n_[3], off_;
+    __device__ __forceinline__ void set_n(int a, double v) { n_[a] = v; }
+    __device__ __forceinline__ void set_off(double v) { off_ = v; }
+    template <typename C> __device__ __forceinline__ double n(const C&, int a) const { return n_[a]; }
+    template <typename C> __device__ __forceinline__ double off(const C&) const { return off_; }
+};
+template <>
+struct PlaneF64<double> {
+    __device__ __forceinline__ void set_n(int, double) {}
+    __device__ __forceinline__ void set_off(double) {}
+    template <typename C> __device__ __forceinline__ double n(const C& c, int a) const { return c.n[a]; }
+    template <typename C> __device__ __forceinline__ double off(const C& c) const { return c.off; }
+};
+
 template <typename R>
 struct Cand {
     R v[3][3];      // vertices in the block frame (centres of the block at 0..3)
@@ -161,8 +179,7 @@ struct Cand {
     R off;          // n . a
     R bound;        // |(off - n.P) - orient3d(a,b,c,P)| <= bound for P in [-1,4]^3
     R delta;        // rounding bound of v
-    double n64[3];  // float64 plane for the hit parameter
-    double off64;
+    PlaneF64<R> p64;  // float64 plane for the hit parameter (the float64 form's own plane)
     int tri;
 };
 
@@ -232,8 +249,8 @@ __device__ void stage_cand(const DevMesh& m, int L, int tri, const int vid[3], c
         ena += 5 * u64 * perm[a] * (fabs(v[0][a]) + 4.0);
     }
 #pragma unroll
-    for (int a = 0; a < 3; a++) C.n64[a] = n[a];
-    C.off64 = off;
+    for (int a = 0; a < 3; a++) C.p64.set_n(a, n[a]);
+    C.p64.set_off(off);
     if constexpr (std::is_same<R, float>::value) {
         const double u32 = 5.9604644775390625e-8;
         float n32[3];
@@ -436,7 +453,20 @@ __device__ __forceinline__ int fast_test(const Cand<R>& C, const R X[3], const R
     return 1;
 }
 
-constexpr int CL_MAXC = 16;  // box-passing candidates taken per link and round
+// Flattened (link, candidate) pairs, per round up to MAXC per link.  The
+// float32 form packs the link's lattice position and direction into the
+// entry (one LDS read per pair fewer) and takes 8 per round, keeping the same
+// LDS size; the float64 form, with larger candidates in LDS, takes 16.
+template <typename R> struct FlatCfg {
+    using T = uint32_t;
+    static constexpr int MAXC = 8;
+    static constexpr bool packed = true;
+};
+template <> struct FlatCfg<double> {
+    using T = uint16_t;
+    static constexpr int MAXC = 16;
+    static constexpr bool packed = false;
+};
 
 // packed nearest-hit key: t in [0,1] as 37-bit fixed point, then the
 // triangle id (27 bits); the minimum key is the nearest hit, ties (equal t to
@@ -533,7 +563,8 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
     __shared__ uint32_t smask[64];
     __shared__ int spre[65];
     __shared__ unsigned halo[36];
-    __shared__ uint16_t flat[64 * CL_MAXC];   // flattened pairs: owner lane | candidate slot << 6
+    // flattened pairs: owner lane | candidate slot << 6 (| link << 12 when packed)
+    __shared__ typename FlatCfg<R>::T flat[64 * FlatCfg<R>::MAXC];
     __shared__ unsigned long long lbest[64];  // nearest hit of each lane's link (packed key)
     __shared__ int sk[64];                    // link of each lane: t | (d + 1) << 8 (2 bits per axis)
     const int L = d.level;
@@ -652,7 +683,8 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
         }
         int cx, cy, cz;
         dirvec(k, cx, cy, cz);
-        sk[lane] = t | ((cx + 1) << 8) | ((cy + 1) << 10) | ((cz + 1) << 12);
+        const int myk = t | ((cx + 1) << 8) | ((cy + 1) << 10) | ((cz + 1) << 12);
+        if (!FlatCfg<R>::packed) sk[lane] = myk;
         const int slo[3] = {geo_min(t & 3, (t & 3) + cx), geo_min((t >> 2) & 3, ((t >> 2) & 3) + cy),
                             geo_min(t >> 4, (t >> 4) + cz)};
         const int shi[3] = {geo_max(t & 3, (t & 3) + cx), geo_max((t >> 2) & 3, ((t >> 2) & 3) + cy),
@@ -666,15 +698,15 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
                  bmask[25 + slo[2]] & bmask[31 + shi[2]];
         }
         while (__any(pm != 0)) {  // uniform
-            // flatten up to CL_MAXC pairs per link over the wave
+            // flatten up to MAXC pairs per link over the wave
             const int pc = __popcll(pm);
-            const int cnt = pc < CL_MAXC ? pc : CL_MAXC;
+            const int cnt = pc < FlatCfg<R>::MAXC ? pc : FlatCfg<R>::MAXC;
             const int inc2 = wave_incl_scan(cnt);
             const int pbase = inc2 - cnt;
             for (int j = 0; j < cnt; j++) {
                 const int slot = __ffsll(pm) - 1;
                 pm &= pm - 1;
-                flat[pbase + j] = (uint16_t)(lane | (slot << 6));
+                flat[pbase + j] = (typename FlatCfg<R>::T)(lane | (slot << 6) | (FlatCfg<R>::packed ? myk << 12 : 0));
             }
             const int P = __shfl(inc2, 63, 64);
             __syncthreads();
@@ -683,8 +715,8 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
             for (int p = lane; p < P; p += 64) {
                 const int fe = flat[p];
                 const int ow = fe & 63;
-                const int cidx = fe >> 6;
-                const int tk = sk[ow];
+                const int cidx = (fe >> 6) & 63;
+                const int tk = FlatCfg<R>::packed ? (int)(fe >> 12) : sk[ow];
                 const int ox = ((tk >> 8) & 3) - 1, oy = ((tk >> 10) & 3) - 1, oz = ((tk >> 12) & 3) - 1;
                 const int Xi[3] = {tk & 3, (tk >> 2) & 3, (tk >> 4) & 3};
                 const R X[3] = {(R)Xi[0], (R)Xi[1], (R)Xi[2]};
@@ -695,8 +727,9 @@ __global__ void __launch_bounds__(64) k_cl_q(DevMesh m, DevLevel d, const int32_
                 unsigned long long kk = KEY_MISS;
                 if (res == 1) {
                     // hit parameter from the float64 plane
-                    const double sX = C.off64 - C.n64[0] * Xi[0] - C.n64[1] * Xi[1] - C.n64[2] * Xi[2];
-                    const double nd = C.n64[0] * ox + C.n64[1] * oy + C.n64[2] * oz;
+                    const double n0 = C.p64.n(C, 0), n1 = C.p64.n(C, 1), n2 = C.p64.n(C, 2);
+                    const double sX = C.p64.off(C) - n0 * Xi[0] - n1 * Xi[1] - n2 * Xi[2];
+                    const double nd = n0 * ox + n1 * oy + n2 * oz;
                     kk = hit_key(sX / nd, C.tri);
                 } else if (res < 0) {
                     // not certain: the link is redone exactly by the deferred pass
