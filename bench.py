@@ -335,7 +335,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="star7m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-links", action="store_true", help="also time the oracle's q on a link sample")
+    ap.add_argument("--no-cpu-links", action="store_true", help="skip the oracle's q on a link sample")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-bounce-back", action="store_true")
     ap.add_argument("--no-moving", action="store_true")
@@ -444,7 +444,7 @@ def main():
     del dn
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(w, out, with_links=args.cpu_links)
+        line["cpu_baseline"] = cpu_baseline(w, out, with_links=not args.no_cpu_links)
     print(json.dumps(line), flush=True)
 
 
