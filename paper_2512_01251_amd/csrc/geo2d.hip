@@ -129,16 +129,28 @@ __device__ bool segment_meets_box(const double* a, const double* b, double x0, d
 }
 
 // kind 0 (ROWS): rows j with j + 1/2 in [ymin, ymax]; kind 1 (LINKS): blocks
-// whose box grown by 1/2 the segment meets.  fill = false counts into cnt,
-// fill = true places e at off[key] + cursor[key]++.
+// whose box grown by 1/2 the segment meets.  FILL = false counts into cnt,
+// FILL = true places e at off[key] + cursor[key]++.  One wave per edge, its
+// lanes splitting the edge's keys (a long edge covers hundreds of rows).
 template <bool FILL>
-__global__ void k2_bins(Dev2Mesh m, Dev2Level d, int kind, double scale, int32_t* cnt, const int32_t* off,
-                        int32_t* cursor, int32_t* val, int64_t cap) {
+__global__ void __launch_bounds__(256) k2_bins(Dev2Mesh m, Dev2Level d, int kind, double scale, int32_t* cnt,
+                                               const int32_t* off, int32_t* cursor, int32_t* val, int64_t cap) {
     const int64_t ny = (int64_t)d.n0[1] << d.level;
     const int nbx = (d.n0[0] >> 2) << d.level, nby = (d.n0[1] >> 2) << d.level;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m.ne; e += gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t e = wave; e < m.ne; e += nwaves) {
         double a[2], b[2];
-        if (!load_edge(m, e, scale, a, b)) continue;
+        if (!load_edge(m, (int)e, scale, a, b)) continue;
+        auto place = [&](int64_t key) {
+            if (!FILL) {
+                atomicAdd(&cnt[key], 1);
+            } else {
+                const int64_t p = (int64_t)off[key] + atomicAdd(&cursor[key], 1);
+                if (p < cap) val[p] = (int32_t)e;
+            }
+        };
         if (kind == 0) {
             // clamped before the conversion (no overflow for any input)
             const double y0 = fmin(fmax(fmin(a[1], b[1]) - 0.5, -1.0), (double)ny);
@@ -146,14 +158,7 @@ __global__ void k2_bins(Dev2Mesh m, Dev2Level d, int kind, double scale, int32_t
             int64_t j0 = (int64_t)ceil(y0), j1 = (int64_t)floor(y1);
             if (j0 < 0) j0 = 0;
             if (j1 > ny - 1) j1 = ny - 1;
-            for (int64_t j = j0; j <= j1; j++) {
-                if (!FILL) {
-                    atomicAdd(&cnt[j], 1);
-                } else {
-                    const int64_t p = (int64_t)off[j] + atomicAdd(&cursor[j], 1);
-                    if (p < cap) val[p] = e;
-                }
-            }
+            for (int64_t j = j0 + lane; j <= j1; j += 64) place(j);
         } else {
             const double x0 = fmin(a[0], b[0]) - 0.5, x1 = fmax(a[0], b[0]) + 0.5;
             const double y0 = fmin(a[1], b[1]) - 0.5, y1 = fmax(a[1], b[1]) + 0.5;
@@ -167,19 +172,14 @@ __global__ void k2_bins(Dev2Mesh m, Dev2Level d, int kind, double scale, int32_t
             if (by0 < 0) by0 = 0;
             if (bx1 > nbx - 1) bx1 = nbx - 1;
             if (by1 > nby - 1) by1 = nby - 1;
-            for (int by = by0; by <= by1; by++)
-                for (int bx = bx0; bx <= bx1; bx++) {
-                    if (!segment_meets_box(a, b, 4.0 * bx - 0.5, 4.0 * bx + 4.5, 4.0 * by - 0.5, 4.0 * by + 4.5))
-                        continue;
-                    const int blk = forest_lookup2(d, bx, by);
-                    if (blk < 0) continue;
-                    if (!FILL) {
-                        atomicAdd(&cnt[blk], 1);
-                    } else {
-                        const int64_t p = (int64_t)off[blk] + atomicAdd(&cursor[blk], 1);
-                        if (p < cap) val[p] = e;
-                    }
-                }
+            const int sx = bx1 - bx0 + 1, sy = by1 - by0 + 1;
+            const int64_t n = (sx > 0 && sy > 0) ? (int64_t)sx * sy : 0;
+            for (int64_t it = lane; it < n; it += 64) {
+                const int bx = bx0 + (int)(it % sx), by = by0 + (int)(it / sx);
+                if (!segment_meets_box(a, b, 4.0 * bx - 0.5, 4.0 * bx + 4.5, 4.0 * by - 0.5, 4.0 * by + 4.5)) continue;
+                const int blk = forest_lookup2(d, bx, by);
+                if (blk >= 0) place(blk);
+            }
         }
     }
 }
@@ -370,6 +370,9 @@ __global__ void __launch_bounds__(64) k2_cl_fill(Dev2Mesh m, Dev2Level d, const 
                                                  int64_t lcap, double scale, const uint16_t* mask,
                                                  const int32_t* off, int64_t cap, int32_t* link_cell,
                                                  uint8_t* link_dir, float* link_q, int32_t* link_edge) {
+    // the block's candidate edges, 64 at a time, staged in LDS by the whole wave
+    __shared__ double sa[64][2], sb[64][2];
+    __shared__ int sid[64];
     const int lane = threadIdx.x;
     for (int64_t b = blockIdx.x; b < d.nblocks; b += gridDim.x) {
         const uint16_t mk = lane < 16 ? mask[16 * b + lane] : 0;
@@ -381,34 +384,62 @@ __global__ void __launch_bounds__(64) k2_cl_fill(Dev2Mesh m, Dev2Level d, const 
             const int v = __shfl_up(incl, o, 64);
             if ((lane & 15) >= o) incl += v;
         }
-        int64_t pos = (int64_t)off[b] + incl - c;
-        if (!mk) continue;
+        const int64_t pos0 = (int64_t)off[b] + incl - c;
+        if (!__any(mk != 0)) continue;  // uniform
         const double X0 = 4 * d.bcoord[2 * b] + (lane & 3) + 0.5, X1 = 4 * d.bcoord[2 * b + 1] + (lane >> 2) + 0.5;
         int e0 = loff[b], e1 = loff[b + 1];
         if (e0 < 0) e0 = 0;
         if (e1 > lcap) e1 = (int)lcap;
+        double best[9];
+        int be[9];
+#pragma unroll
         for (int k = 0; k < 9; k++) {
-            if (!((mk >> k) & 1)) continue;
-            const double c0 = k % 3 - 1, c1 = k / 3 - 1;
-            double best = 2.0;
-            int be = -1;
-            for (int q = e0; q < e1; q++) {
-                const int e = lval[q];
-                if (e < 0 || e >= m.ne) continue;
+            best[k] = 2.0;
+            be[k] = -1;
+        }
+        for (int c0 = e0; c0 < e1; c0 += 64) {  // uniform
+            const int nc = e1 - c0 < 64 ? e1 - c0 : 64;
+            __syncthreads();
+            if (lane < nc) {
+                const int e = lval[c0 + lane];
                 double a[2], bb[2];
-                if (!load_edge(m, e, scale, a, bb)) continue;
-                const double t = link_hit2(a, bb, X0, X1, c0, c1);
-                if (t < 0.0) continue;
-                if (t < best || (t == best && e < be)) {
-                    best = t;
-                    be = e;
+                const bool ok = e >= 0 && e < m.ne && load_edge(m, e, scale, a, bb);
+                sid[lane] = ok ? e : -1;
+                sa[lane][0] = a[0];
+                sa[lane][1] = a[1];
+                sb[lane][0] = bb[0];
+                sb[lane][1] = bb[1];
+            }
+            __syncthreads();
+            if (mk) {
+#pragma unroll
+                for (int k = 0; k < 9; k++) {
+                    if (!((mk >> k) & 1)) continue;
+                    const double cx = k % 3 - 1, cy = k / 3 - 1;
+                    for (int q = 0; q < nc; q++) {
+                        const int e = sid[q];
+                        if (e < 0) continue;
+                        const double a[2] = {sa[q][0], sa[q][1]}, bb[2] = {sb[q][0], sb[q][1]};
+                        const double t = link_hit2(a, bb, X0, X1, cx, cy);
+                        if (t < 0.0) continue;
+                        if (t < best[k] || (t == best[k] && e < be[k])) {
+                            best[k] = t;
+                            be[k] = e;
+                        }
+                    }
                 }
             }
+        }
+        if (!mk) continue;
+        int64_t pos = pos0;
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            if (!((mk >> k) & 1)) continue;
             if (pos < cap) {
                 link_cell[pos] = (int32_t)(16 * b + lane);
                 link_dir[pos] = (uint8_t)k;
-                link_q[pos] = be >= 0 ? (float)best : -1.0f;
-                link_edge[pos] = be;
+                link_q[pos] = be[k] >= 0 ? (float)best[k] : -1.0f;
+                link_edge[pos] = be[k];
             }
             pos++;
         }
@@ -500,7 +531,7 @@ int geo2_build_bins(const geo2_mesh* mesh, const geo2_level* lv, int32_t kind, g
     const Dev2Level d = dev2_level(lv);
     const double scale = ldexp(1.0, lv->level);
     const int kk = kind == GEO_BINS_ROWS ? 0 : 1;
-    const unsigned g = grid1(mesh->ne, 256, 8192);
+    const unsigned g = grid1((int64_t)mesh->ne * 64, 256, 8192);  // one wave per edge
     if (mesh->ne > 0) k2_bins<false><<<g, 256, 0, s>>>(m, d, kk, scale, cnt, nullptr, nullptr, nullptr, 0);
     GEO_LAUNCH_CHECK();
     rc = geo_scan_exclusive(cnt, bins->off, nkeys, partials, s);
