@@ -187,10 +187,12 @@ def bounce_back_bench(emb, dn, reps=20):
     block map, the dense q of every boundary block, and per link the
     populations read (one for simple, two for interpolated bounce-back) and
     the one written.  For scale: one device copy of the whole population
-    array (the least traffic a full solver step on the level moves)."""
+    array (the least traffic a full solver step on the level moves).  The
+    neighbours come from the level's neighbour table (built once, timed
+    apart); the interpolated form walking the forest instead is timed too."""
     import torch
-    from paper_2512_01251_amd import (GEO_KT_IBB, geo_ibb, geo_kernel_timer, geo_kernel_timer_read,
-                                      make_level)
+    from paper_2512_01251_amd import (GEO_KT_IBB, geo_block_neighbours, geo_ibb, geo_kernel_timer,
+                                      geo_kernel_timer_read, make_level)
     from synth.populations import lattice_weights
     rec = emb.levels[-1]
     nb = int(rec.bcoord.shape[0])
@@ -206,23 +208,34 @@ def bounce_back_bench(emb, dn, reps=20):
     d_fb = torch.zeros(1, dtype=torch.int64, device=dev)
     res = {"blocks": nb, "boundary_blocks": dn.nbnd, "links": emb.links.n, "dtype": "f32",
            "populations_gb": 2 * f_post.numel() * 4 / 1e9}
+    # the level's neighbour table, built once per geometry (a solver keeps it)
+    nbr = torch.empty((nb, 27), dtype=torch.int32, device=dev)
+    geo_block_neighbours(lvd, nbr)
+    _sync()
+    s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s_ev.record()
+    geo_block_neighbours(lvd, nbr)
+    e_ev.record()
+    _sync()
+    res["neighbour_table_ms"] = s_ev.elapsed_time(e_ev)
     base = 4 * nb + dn.nbnd * dn.q.shape[1] * 64 * 4
-    for name, interp, per_link in (("sbb", False, 8), ("ibb", True, 12)):
-        geo_ibb(lvd, rec.solid, dn.block_map, dn.q, dn.nbnd, emb.lattice, interp, f_post, f_new, d_fb)
+    for name, interp, per_link, table in (("sbb", False, 8, nbr), ("ibb", True, 12, nbr),
+                                          ("ibb_forest_walk", True, 12, None)):
+        geo_ibb(lvd, rec.solid, dn.block_map, dn.q, dn.nbnd, emb.lattice, interp, f_post, f_new, d_fb, nbr=table)
         _sync()
         geo_kernel_timer(GEO_KT_IBB, True)
         for _ in range(reps):
-            geo_ibb(lvd, rec.solid, dn.block_map, dn.q, dn.nbnd, emb.lattice, interp, f_post, f_new)
+            geo_ibb(lvd, rec.solid, dn.block_map, dn.q, dn.nbnd, emb.lattice, interp, f_post, f_new, nbr=table)
         ms, n = geo_kernel_timer_read(GEO_KT_IBB)
         geo_kernel_timer(GEO_KT_IBB, False)
         ms /= max(n, 1)
-        nbytes = base + per_link * emb.links.n
+        nbytes = base + per_link * emb.links.n + (27 * 4 * dn.nbnd if interp and table is not None else 0)
         res[f"{name}_ms"] = ms
         res[f"{name}_bytes"] = nbytes
         res[f"{name}_gb_per_s"] = nbytes / (ms * 1e-3) / 1e9
-    res["fallback_links"] = int(d_fb.item())
+    res["fallback_links"] = int(d_fb.item()) // 2  # accumulated over both interpolated warm-up calls
     res["ibb_over_sbb"] = res["ibb_ms"] / res["sbb_ms"]
-    s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    del nbr
     f_new.copy_(f_post)
     s_ev.record()
     for _ in range(3):

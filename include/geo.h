@@ -266,10 +266,23 @@ int geo_links_dense(const geo_level* lv, int64_t n_links, const int32_t* link_ce
  *   block_map, dense_q: from geo_links_dense on this level and lattice
  *     (lattice 19 or 27); nbnd = boundary blocks that dense_q holds (blocks
  *     mapped to an index >= nbnd are skipped).
+ *   nbr: the level's neighbour table from geo_block_neighbours, or NULL
+ *     (the neighbours are then found through the forest).
  */
 int geo_ibb(const geo_level* lv, const uint64_t* solid, const int32_t* block_map, const float* dense_q,
-            int64_t nbnd, int32_t lattice, int32_t interpolate, int32_t dtype, const void* f_post,
-            void* f_new, uint64_t* d_fallback, geo_stream_t stream);
+            int64_t nbnd, const int32_t* nbr, int32_t lattice, int32_t interpolate, int32_t dtype,
+            const void* f_post, void* f_new, uint64_t* d_fallback, geo_stream_t stream);
+
+/*
+ * The 27-neighbourhood of every block of one level: the neighbour indices a
+ * block-structured solver keeps (Methodology, "GPU-based Forest-of-Octrees":
+ * blocks store the indices of a full halo of neighbours).
+ *   nbr[b * 27 + o] (device int32[nblocks][27], written) = index of the
+ *   same-level block at offset o = (ox+1) + 3 (oy+1) + 9 (oz+1) from block b
+ *   (o = 13 is b itself), -1 where the forest has no such block, -2 outside
+ *   the domain.
+ */
+int geo_block_neighbours(const geo_level* lv, int32_t* nbr, geo_stream_t stream);
 
 /* ------------------------------------------------------------------------
  * 2D: quadtrees (the paper's discussion of octrees holds for quadtrees in

@@ -30,7 +30,7 @@ GEO_MAX_LEVELS = 12
 GEO_MAX_RES = 32767
 
 EXPORTS = ["geo_workspace_size", "geo_nprop", "geo_level0_blocks", "geo_build_bins", "geo_voxelize",
-           "geo_refine_flags", "geo_cutlinks", "geo_cutlinks_backward", "geo_links_dense", "geo_ibb", "geo_solid_change", "geo2_level0_blocks", "geo2_build_bins",
+           "geo_refine_flags", "geo_cutlinks", "geo_cutlinks_backward", "geo_links_dense", "geo_ibb", "geo_block_neighbours", "geo_solid_change", "geo2_level0_blocks", "geo2_build_bins",
            "geo2_voxelize", "geo2_refine_flags", "geo2_cutlinks", "geo_kernel_timer", "geo_kernel_timer_read", "geo_version"]
 
 
@@ -85,7 +85,8 @@ def lib():
         L.geo_cutlinks.argtypes = [MP, LP, BP, BP, i32, i32, P, i64, P, P, P, P, P, P, P, sz, P]
         L.geo_cutlinks_backward.argtypes = [MP, LP, i64, P, P, P, P, P, P]
         L.geo_links_dense.argtypes = [LP, i64, P, P, P, P, i32, i64, P, P, P, P, P, sz, P]
-        L.geo_ibb.argtypes = [LP, P, P, P, i64, i32, i32, i32, P, P, P, P]
+        L.geo_ibb.argtypes = [LP, P, P, P, i64, P, i32, i32, i32, P, P, P, P]
+        L.geo_block_neighbours.argtypes = [LP, P, P]
         L.geo_solid_change.argtypes = [i64, P, P, P, P, P, P]
         M2, L2 = C.POINTER(geo2_mesh), C.POINTER(geo2_level)
         L.geo2_level0_blocks.argtypes = [P, P, P]
@@ -238,14 +239,19 @@ def geo_links_dense(level: geo_level, n_links: int, link_cell, link_dir, link_q,
     _check(rc, "geo_links_dense")
 
 
+def geo_block_neighbours(level: geo_level, nbr, stream=None):
+    _check(lib().geo_block_neighbours(C.byref(level), _ptr(nbr), _stream(stream)), "geo_block_neighbours")
+
+
 def geo_ibb(level: geo_level, solid, block_map, dense_q, nbnd: int, lattice: int, interpolate: bool, f_post,
-            f_new, d_fallback=None, stream=None):
+            f_new, d_fallback=None, stream=None, nbr=None):
     import torch
     if f_post.dtype != f_new.dtype or f_post.dtype not in (torch.float32, torch.float64):
         raise GeoError("geo_ibb: f_post and f_new must both be float32 or both float64")
     dt = GEO_F64 if f_post.dtype == torch.float64 else GEO_F32
-    rc = lib().geo_ibb(C.byref(level), _ptr(solid), _ptr(block_map), _ptr(dense_q), int(nbnd), int(lattice),
-                       int(bool(interpolate)), dt, _ptr(f_post), _ptr(f_new), _ptr(d_fallback), _stream(stream))
+    rc = lib().geo_ibb(C.byref(level), _ptr(solid), _ptr(block_map), _ptr(dense_q), int(nbnd), _ptr(nbr),
+                       int(lattice), int(bool(interpolate)), dt, _ptr(f_post), _ptr(f_new), _ptr(d_fallback),
+                       _stream(stream))
     _check(rc, "geo_ibb")
 
 

@@ -190,9 +190,15 @@ int geo_links_dense(const geo_level* lv, int64_t n_links, const int32_t* link_ce
                               dense_q, dense_tri, d_nbnd, ws, ws_bytes, (hipStream_t)stream);
 }
 
+int geo_block_neighbours(const geo_level* lv, int32_t* nbr, geo_stream_t stream) {
+    if (!check_level(lv)) return GEO_ERR_ARG;
+    if (lv->nblocks > 0 && !nbr) return GEO_ERR_ARG;
+    return launch_block_nbr(dev_level(lv), nbr, (hipStream_t)stream);
+}
+
 int geo_ibb(const geo_level* lv, const uint64_t* solid, const int32_t* block_map, const float* dense_q,
-            int64_t nbnd, int32_t lattice, int32_t interpolate, int32_t dtype, const void* f_post, void* f_new,
-            uint64_t* d_fallback, geo_stream_t stream) {
+            int64_t nbnd, const int32_t* nbr, int32_t lattice, int32_t interpolate, int32_t dtype,
+            const void* f_post, void* f_new, uint64_t* d_fallback, geo_stream_t stream) {
     if (!check_level(lv) || nbnd < 0) return GEO_ERR_ARG;
     if ((lattice != 19 && lattice != 27) || (dtype != GEO_F32 && dtype != GEO_F64)) return GEO_ERR_ARG;
     if (lv->nblocks > 0 && (!solid || !block_map || !f_post || !f_new)) return GEO_ERR_ARG;
@@ -204,7 +210,7 @@ int geo_ibb(const geo_level* lv, const uint64_t* solid, const int32_t* block_map
         const uintptr_t a = reinterpret_cast<uintptr_t>(f_post), b = reinterpret_cast<uintptr_t>(f_new);
         if (a < b + bytes && b < a + bytes) return GEO_ERR_ARG;
     }
-    return launch_ibb(dev_level(lv), solid, block_map, dense_q, nbnd, lattice, interpolate, dtype, f_post, f_new,
+    return launch_ibb(dev_level(lv), solid, block_map, dense_q, nbnd, nbr, lattice, interpolate, dtype, f_post, f_new,
                       reinterpret_cast<unsigned long long*>(d_fallback), (hipStream_t)stream);
 }
 

@@ -100,7 +100,8 @@ __device__ __forceinline__ void ibb_slots(const float* q, const T* __restrict__ 
 template <typename T, int LAT, bool INTERP>
 __global__ void __launch_bounds__(64) k_ibb(DevLevel d, const uint64_t* __restrict__ solid,
                                             const int32_t* __restrict__ block_map, const float* __restrict__ dense_q,
-                                            int64_t nbnd, const T* __restrict__ f_post, T* __restrict__ f_new,
+                                            int64_t nbnd, const int32_t* __restrict__ nbr_table,
+                                            const T* __restrict__ f_post, T* __restrict__ f_new,
                                             unsigned long long* d_fallback) {
     constexpr int QD = LAT == 27 ? 26 : 18, QF = QD + 1, C3 = (QD + 2) / 3;
     __shared__ int nbr[27];          // neighbour block per offset (ox+1) + 3 (oy+1) + 9 (oz+1), < 0 if none
@@ -135,7 +136,9 @@ __global__ void __launch_bounds__(64) k_ibb(DevLevel d, const uint64_t* __restri
                 __syncthreads();
                 if (lane < 27) {
                     int n = (int)b;
-                    if (lane != 13)
+                    if (nbr_table)
+                        n = nbr_table[b * 27 + lane];  // the level's neighbour table (one coalesced read)
+                    else if (lane != 13)
                         n = forest_lookup(d, d.bcoord[3 * b] + lane % 3 - 1, d.bcoord[3 * b + 1] + (lane / 3) % 3 - 1,
                                           d.bcoord[3 * b + 2] + lane / 9 - 1);
                     nbr[lane] = n;
@@ -161,21 +164,42 @@ __global__ void __launch_bounds__(64) k_ibb(DevLevel d, const uint64_t* __restri
 
 template <typename T, int LAT>
 void launch_ibb_t(unsigned g, const DevLevel& d, const uint64_t* solid, const int32_t* block_map,
-                  const float* dense_q, int64_t nbnd, int interpolate, const void* f_post, void* f_new,
-                  unsigned long long* d_fallback, hipStream_t s) {
+                  const float* dense_q, int64_t nbnd, const int32_t* nbr, int interpolate, const void* f_post,
+                  void* f_new, unsigned long long* d_fallback, hipStream_t s) {
     const T* fi = static_cast<const T*>(f_post);
     T* fo = static_cast<T*>(f_new);
     if (interpolate)
-        k_ibb<T, LAT, true><<<g, 64, 0, s>>>(d, solid, block_map, dense_q, nbnd, fi, fo, d_fallback);
+        k_ibb<T, LAT, true><<<g, 64, 0, s>>>(d, solid, block_map, dense_q, nbnd, nbr, fi, fo, d_fallback);
     else
-        k_ibb<T, LAT, false><<<g, 64, 0, s>>>(d, solid, block_map, dense_q, nbnd, fi, fo, d_fallback);
+        k_ibb<T, LAT, false><<<g, 64, 0, s>>>(d, solid, block_map, dense_q, nbnd, nbr, fi, fo, d_fallback);
+}
+
+// the 27 same-level neighbours of every block (offset 13 is the block itself)
+__global__ void k_block_nbr(DevLevel d, int32_t* nbr) {
+    const int64_t n = (int64_t)d.nblocks * 27;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = i / 27;
+        const int o = (int)(i - b * 27);
+        nbr[i] = o == 13 ? (int32_t)b
+                         : forest_lookup(d, d.bcoord[3 * b] + o % 3 - 1, d.bcoord[3 * b + 1] + (o / 3) % 3 - 1,
+                                         d.bcoord[3 * b + 2] + o / 9 - 1);
+    }
 }
 
 }  // namespace
 
+int launch_block_nbr(const DevLevel& d, int32_t* nbr, hipStream_t s) {
+    if (d.nblocks == 0) return GEO_OK;
+    int64_t g = ((int64_t)d.nblocks * 27 + 255) / 256;
+    if (g > 65536) g = 65536;
+    k_block_nbr<<<(unsigned)g, 256, 0, s>>>(d, nbr);
+    GEO_LAUNCH_CHECK();
+    return GEO_OK;
+}
+
 int launch_ibb(const DevLevel& d, const uint64_t* solid, const int32_t* block_map, const float* dense_q,
-               int64_t nbnd, int lattice, int interpolate, int dtype, const void* f_post, void* f_new,
-               unsigned long long* d_fallback, hipStream_t s) {
+               int64_t nbnd, const int32_t* nbr, int lattice, int interpolate, int dtype, const void* f_post,
+               void* f_new, unsigned long long* d_fallback, hipStream_t s) {
     if (d.nblocks == 0 || nbnd == 0) return GEO_OK;
     const int64_t chunks = ((int64_t)d.nblocks + 63) / 64;
     const int64_t g = chunks < IBB_GRID_MAX ? chunks : IBB_GRID_MAX;
@@ -183,14 +207,14 @@ int launch_ibb(const DevLevel& d, const uint64_t* solid, const int32_t* block_ma
     const unsigned gu = (unsigned)g;
     if (dtype == GEO_F64) {
         if (lattice == 27)
-            launch_ibb_t<double, 27>(gu, d, solid, block_map, dense_q, nbnd, interpolate, f_post, f_new, d_fallback, s);
+            launch_ibb_t<double, 27>(gu, d, solid, block_map, dense_q, nbnd, nbr, interpolate, f_post, f_new, d_fallback, s);
         else
-            launch_ibb_t<double, 19>(gu, d, solid, block_map, dense_q, nbnd, interpolate, f_post, f_new, d_fallback, s);
+            launch_ibb_t<double, 19>(gu, d, solid, block_map, dense_q, nbnd, nbr, interpolate, f_post, f_new, d_fallback, s);
     } else {
         if (lattice == 27)
-            launch_ibb_t<float, 27>(gu, d, solid, block_map, dense_q, nbnd, interpolate, f_post, f_new, d_fallback, s);
+            launch_ibb_t<float, 27>(gu, d, solid, block_map, dense_q, nbnd, nbr, interpolate, f_post, f_new, d_fallback, s);
         else
-            launch_ibb_t<float, 19>(gu, d, solid, block_map, dense_q, nbnd, interpolate, f_post, f_new, d_fallback, s);
+            launch_ibb_t<float, 19>(gu, d, solid, block_map, dense_q, nbnd, nbr, interpolate, f_post, f_new, d_fallback, s);
     }
     kt_record(GEO_KT_IBB, s, true);
     GEO_LAUNCH_CHECK();

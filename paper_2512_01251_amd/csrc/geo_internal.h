@@ -300,9 +300,10 @@ size_t geo_dense_ws_bytes(int64_t nb);
 int launch_links_dense(int64_t nb, int64_t n_links, const int32_t* link_cell, const uint8_t* link_dir,
                        const float* link_q, const int32_t* link_tri, int lattice, int64_t cap, int32_t* block_map,
                        float* dense_q, int32_t* dense_tri, int64_t* d_nbnd, void* ws, size_t ws_bytes, hipStream_t s);
+int launch_block_nbr(const DevLevel& d, int32_t* nbr, hipStream_t s);
 int launch_ibb(const DevLevel& d, const uint64_t* solid, const int32_t* block_map, const float* dense_q,
-               int64_t nbnd, int lattice, int interpolate, int dtype, const void* f_post, void* f_new,
-               unsigned long long* d_fallback, hipStream_t s);
+               int64_t nbnd, const int32_t* nbr, int lattice, int interpolate, int dtype, const void* f_post,
+               void* f_new, unsigned long long* d_fallback, hipStream_t s);
 int launch_solid_change(int64_t n, const uint64_t* prev, const uint64_t* cur, uint64_t* spawned, uint64_t* covered,
                         unsigned long long* d_counts, hipStream_t s);
 size_t geo2_bins_ws_bytes(int64_t nkeys);

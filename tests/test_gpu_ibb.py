@@ -128,3 +128,43 @@ def test_bounce_back_on_the_cut_link_table(name):
     near_half = int(np.count_nonzero(np.abs(rl["q"] - 0.5) <= 2e-5))
     assert abs(gfb - ofb) <= near_half
     say(f"[ibb] table {name} ok: {gfb} fallbacks (oracle {ofb}), max err {err:.2e}")
+
+
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_block_neighbours_and_bounce_back_with_the_table(name):
+    """The level's 27-neighbour table against a search over the oracle's block
+    list (-1 missing, -2 outside the domain); bounce-back reading the table is
+    identical to bounce-back walking the forest."""
+    import torch
+    from paper_2512_01251_amd import geo_block_neighbours
+    from paper_2512_01251_amd.pipeline import links_dense
+    w, ref, emb = _setup(name)
+    r = ref["levels"][-1]
+    bc = r["bcoord"].astype(np.int64)
+    nb = len(bc)
+    say(f"[ibb] neighbour table {name}: {nb} blocks")
+    nbr = torch.empty((nb, 27), dtype=torch.int32, device="cuda")
+    geo_block_neighbours(_level(emb), nbr)
+    got = nbr.cpu().numpy()
+    index = {tuple(x): i for i, x in enumerate(bc)}
+    dims = np.array(w.n0) // 4 * 2 ** w.lf
+    want = np.empty((nb, 27), np.int64)
+    for b in range(nb):
+        for o in range(27):
+            p = bc[b] + np.array([o % 3 - 1, (o // 3) % 3 - 1, o // 9 - 1])
+            want[b, o] = -2 if (np.any(p < 0) or np.any(p >= dims)) else index.get(tuple(p), -1)
+    assert np.array_equal(got, want)
+    dense = links_dense(emb)
+    fpost = torch.from_numpy(populations.populations(nb, w.lattice, seed=41)).cuda()
+    fnew = torch.from_numpy(populations.populations(nb, w.lattice, seed=42)).cuda()
+    from paper_2512_01251_amd import geo_ibb
+    outs = []
+    for table in (None, nbr):
+        out = fnew.clone()
+        d_fb = torch.zeros(1, dtype=torch.int64, device="cuda")
+        geo_ibb(_level(emb), emb.levels[-1].solid, dense.block_map, dense.q, dense.nbnd, w.lattice, True, fpost,
+                out, d_fb, nbr=table)
+        torch.cuda.synchronize()
+        outs.append((out.cpu().numpy(), int(d_fb.item())))
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+    say(f"[ibb] neighbour table {name} ok")

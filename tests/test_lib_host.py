@@ -240,19 +240,20 @@ def test_bounce_back_arguments_are_checked_on_the_host(geo):
         lv.n0[a] = 32
     lv.level = 0
     lv.nblocks = 0
-    assert L.geo_ibb(C.byref(lv), None, None, None, 0, 27, 1, geo.GEO_F32, None, None, None, None) == geo.GEO_OK
-    assert L.geo_ibb(C.byref(lv), None, None, None, 0, 20, 1, geo.GEO_F32, None, None, None, None) == geo.GEO_ERR_ARG
-    assert L.geo_ibb(C.byref(lv), None, None, None, 0, 19, 1, 7, None, None, None, None) == geo.GEO_ERR_ARG
+    assert L.geo_ibb(C.byref(lv), None, None, None, 0, None, 27, 1, geo.GEO_F32, None, None, None, None) == geo.GEO_OK
+    assert L.geo_ibb(C.byref(lv), None, None, None, 0, None, 20, 1, geo.GEO_F32, None, None, None, None) == geo.GEO_ERR_ARG
+    assert L.geo_ibb(C.byref(lv), None, None, None, 0, None, 19, 1, 7, None, None, None, None) == geo.GEO_ERR_ARG
     lv.nblocks = 8
     bc = (C.c_int32 * 24)()
     lv.bcoord = C.addressof(bc)
     buf = (C.c_float * (8 * 27 * 64 * 2))()
     p = C.addressof(buf)
     # f_new overlapping f_post
-    assert L.geo_ibb(C.byref(lv), p, p, p, 1, 27, 1, geo.GEO_F32, p, p + 64, None, None) == geo.GEO_ERR_ARG
+    assert L.geo_ibb(C.byref(lv), p, p, p, 1, None, 27, 1, geo.GEO_F32, p, p + 64, None, None) == geo.GEO_ERR_ARG
     # missing solid bits
-    assert L.geo_ibb(C.byref(lv), None, p, p, 1, 27, 1, geo.GEO_F32, p, p + 8 * 27 * 64 * 4, None,
+    assert L.geo_ibb(C.byref(lv), None, p, p, 1, None, 27, 1, geo.GEO_F32, p, p + 8 * 27 * 64 * 4, None,
                      None) == geo.GEO_ERR_ARG
+    assert L.geo_block_neighbours(C.byref(lv), None, None) == geo.GEO_ERR_ARG
 
 
 def test_solid_change_arguments_are_checked_on_the_host(geo):
