@@ -114,8 +114,9 @@ typedef struct {
 } geo_level;
 
 /* Compressed bins (CSR).  ROWS: one key per x-row line (j, k) of the level,
- * key = j + ny * k with ny = n0y 2^L (lines of the whole domain); LINKS: one
- * key per block of the level. */
+ * key = j + ny * k with ny = n0y 2^L (lines of the whole domain; they do not
+ * read the level's blocks, so they may be built before those are known);
+ * LINKS: one key per block of the level. */
 typedef struct {
     int32_t kind;     /* GEO_BINS_ROWS or GEO_BINS_LINKS                          */
     int64_t nkeys;    /* ROWS: ny*nz lines; LINKS: nblocks                          */

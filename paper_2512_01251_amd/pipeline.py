@@ -67,6 +67,9 @@ class Embedder:
         self.device = torch.device(device)
         self.ws = torch.empty(0, dtype=torch.uint8, device=self.device)
         self.caps: dict = {}                 # remembered buffer capacities
+        # pinned host word for the per-level block count (read without a
+        # stream-wide wait)
+        self._host_n = torch.zeros(1, dtype=torch.int64, pin_memory=self.device.type == "cuda")
         self.events = None   # list of (name, start_event, end_event) when timing
 
     # -- helpers ---------------------------------------------------------------
@@ -112,13 +115,21 @@ class Embedder:
         out = Embedding(tuple(n0), lf, lattice)
         child_maps = []
         rows = None
-        for L in range(lf + 1):
-            lvd = make_level(n0, L, bcoord, child_maps)
-            rec = Level(L, bcoord)
+
+        def row_bins(L, lvd):
+            # ROWS bins depend on the level, not on its blocks: the next level's
+            # are enqueued before the host waits for that level's block count
             nkeys = (n0[1] << L) * (n0[2] << L)
             key = ("rows", L)
             cap = self.caps.get(key, max(4096, 2 * mesh.nt))
-            rec.rows_off, val = self._bins(mesh, lvd, GEO_BINS_ROWS, prec, nkeys, stats, cap, cnt(L), f"rows{L}")
+            off, val = self._bins(mesh, lvd, GEO_BINS_ROWS, prec, nkeys, stats, cap, cnt(L), f"rows{L}")
+            return nkeys, key, cap, off, val
+
+        ahead = row_bins(0, make_level(n0, 0, bcoord, child_maps))
+        for L in range(lf + 1):
+            lvd = make_level(n0, L, bcoord, child_maps)
+            rec = Level(L, bcoord)
+            nkeys, key, cap, rec.rows_off, val = ahead
             checks.append((L, cap, key, lambda c, rec=rec, val=val: setattr(rec, "rows_val", val[:c])))
             rows = make_bins(GEO_BINS_ROWS, nkeys, rec.rows_off, val, cap, cnt(L))
             rec.rows_val = val
@@ -136,8 +147,14 @@ class Embedder:
                 with self._timed(f"refine{L}"):
                     geo_refine_flags(lvd, rec.solid, n_prop, rec.bclass, rec.refine, rec.child_map, child,
                                      d_n, ws)
-                nchild = int(d_n.item())
+                self._host_n.copy_(d_n, non_blocking=True)
+                counted = torch.cuda.Event()
+                counted.record()
                 child_maps.append(rec.child_map)
+                empty = torch.empty((0, 3), dtype=torch.int32, device=dev)
+                ahead = row_bins(L + 1, make_level(n0, L + 1, empty, child_maps))
+                counted.synchronize()
+                nchild = int(self._host_n[0])
                 bcoord = child[:nchild]
             out.levels.append(rec)
         if with_links:
