@@ -54,6 +54,7 @@ class Embedder2D:
         self.device = torch.device(device)
         self.ws = torch.empty(0, dtype=torch.uint8, device=self.device)
         self.caps: dict = {}
+        self._host_n = torch.zeros(1, dtype=torch.int64, pin_memory=self.device.type == "cuda")
 
     def _workspace(self, nbytes: int) -> torch.Tensor:
         if self.ws.numel() < nbytes:
@@ -88,13 +89,21 @@ class Embedder2D:
         out = Embedding2D(tuple(n0), lf)
         child_maps = []
         rows = None
-        for L in range(lf + 1):
-            lvd = make_level2(n0, L, bcoord, child_maps)
-            rec = Level2D(L, bcoord)
+
+        def row_bins(L, lvd):
+            # ROWS bins depend on the level, not on its blocks: the next level's
+            # are enqueued before the host waits for that level's block count
             nkeys = n0[1] << L
             key = ("rows", L)
             cap = self.caps.get(key, max(1024, 4 * edges.shape[0]))
-            rows, rec.rows_off, val = self._bins(mesh, lvd, GEO_BINS_ROWS, nkeys, cap, cnt(L))
+            bins, off, val = self._bins(mesh, lvd, GEO_BINS_ROWS, nkeys, cap, cnt(L))
+            return key, cap, bins, off, val
+
+        ahead = row_bins(0, make_level2(n0, 0, bcoord, child_maps))
+        for L in range(lf + 1):
+            lvd = make_level2(n0, L, bcoord, child_maps)
+            rec = Level2D(L, bcoord)
+            key, cap, rows, rec.rows_off, val = ahead
             rec.rows_val = val
             checks.append((L, cap, key, lambda c, rec=rec, val=val: setattr(rec, "rows_val", val[:c])))
             rec.solid = torch.empty(lvd.nblocks, dtype=torch.int16, device=dev)
@@ -108,8 +117,14 @@ class Embedder2D:
                 d_n = cnt(lf + 1 + L)
                 ws = self._workspace(geo_workspace_size(GEO_CALL2_REFINE, nb, 0))
                 geo2_refine_flags(lvd, rec.solid, n_prop, rec.bclass, rec.refine, rec.child_map, child, d_n, ws)
-                nchild = int(d_n.item())
+                self._host_n.copy_(d_n, non_blocking=True)
+                counted = torch.cuda.Event()
+                counted.record()
                 child_maps.append(rec.child_map)
+                empty = torch.empty((0, 2), dtype=torch.int32, device=dev)
+                ahead = row_bins(L + 1, make_level2(n0, L + 1, empty, child_maps))
+                counted.synchronize()
+                nchild = int(self._host_n[0])
                 bcoord = child[:nchild]
             out.levels.append(rec)
         if with_links:
