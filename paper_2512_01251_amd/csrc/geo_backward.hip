@@ -5,9 +5,11 @@
 // lambda_j dv (barycentric coordinate of the hit point), and the hit slides
 // along d until n.(dq d) = n.(lambda_j dv), so dq/dv_j = lambda_j n / (n.d).
 // One thread per link; float64 arithmetic.  Contributions are summed per
-// vertex in an LDS table first (links next to each other in the table come
-// from neighbouring cells and hit the same few triangles), then each distinct
-// vertex of a round takes one float32 atomic add per component in HBM.
+// vertex before they reach HBM: runs of one vertex among consecutive lanes by
+// segmented prefix sums, then per round of 256 links in an LDS table (links
+// next to each other in the table come from neighbouring cells and hit the
+// same few triangles); each distinct vertex of a round takes one float32
+// atomic add per component in HBM.
 #include "geo_internal.h"
 
 namespace {
@@ -16,6 +18,7 @@ constexpr int BW_THREADS = 256;
 constexpr int BW_SLOTS = 1024;  // > 3 * BW_THREADS: a round never fills the table
 
 __device__ __forceinline__ unsigned bw_hash(int v) { return ((unsigned)v * 2654435761u) >> 22; }
+
 
 __global__ void __launch_bounds__(BW_THREADS) k_backward(DevMesh m, DevLevel d, int64_t n_links,
                                                          const int32_t* link_cell, const uint8_t* link_dir,
@@ -75,17 +78,41 @@ __global__ void __launch_bounds__(BW_THREADS) k_backward(DevMesh m, DevLevel d, 
                 }
             }
         }
-        // sum the round's contributions per vertex in LDS (open addressing)
+        // Neighbouring links of the table (one cell, successive directions)
+        // often share a vertex: runs of equal vertex ids among consecutive
+        // lanes are summed first (segmented prefix sums), and only the last
+        // lane of a run adds into the LDS table (open addressing).
+        const int lane = threadIdx.x & 63;
         for (int j = 0; j < 3; j++) {
             const int v = vid[j];
-            if (v < 0) continue;
+            float c0 = v >= 0 ? contrib[j][0] : 0.0f, c1 = v >= 0 ? contrib[j][1] : 0.0f,
+                  c2 = v >= 0 ? contrib[j][2] : 0.0f;
+            const int vprev = __shfl_up(v, 1, 64);
+            int head = (lane == 0 || vprev != v) ? 1 : 0;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const float u0 = __shfl_up(c0, o, 64), u1 = __shfl_up(c1, o, 64), u2 = __shfl_up(c2, o, 64);
+                const int hu = __shfl_up(head, o, 64);
+                if (lane >= o) {
+                    if (!head) {
+                        c0 += u0;
+                        c1 += u1;
+                        c2 += u2;
+                    }
+                    head |= hu;
+                }
+            }
+            const int vnext = __shfl_down(v, 1, 64);
+            if (v < 0 || !(lane == 63 || vnext != v)) continue;
             unsigned slot = bw_hash(v);
             while (true) {
                 const int prev = atomicCAS(&skey[slot], -1, v);
                 if (prev == -1 || prev == v) break;
                 slot = (slot + 1) & (BW_SLOTS - 1);
             }
-            for (int a = 0; a < 3; a++) atomicAdd(&sval[slot][a], contrib[j][a]);
+            atomicAdd(&sval[slot][0], c0);
+            atomicAdd(&sval[slot][1], c1);
+            atomicAdd(&sval[slot][2], c2);
         }
         __syncthreads();
         // one global add per distinct vertex and component, then clear
