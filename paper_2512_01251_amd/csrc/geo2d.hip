@@ -175,7 +175,9 @@ __global__ void __launch_bounds__(256) k2_bins(Dev2Mesh m, Dev2Level d, int kind
             const int sx = bx1 - bx0 + 1, sy = by1 - by0 + 1;
             const int64_t n = (sx > 0 && sy > 0) ? (int64_t)sx * sy : 0;
             for (int64_t it = lane; it < n; it += 64) {
-                const int bx = bx0 + (int)(it % sx), by = by0 + (int)(it / sx);
+                // n < 2^31 here (at most 8192^2 blocks on a level): 32-bit division
+                const unsigned u = (unsigned)it, q = u / (unsigned)sx;
+                const int bx = bx0 + (int)(u - q * (unsigned)sx), by = by0 + (int)q;
                 if (!segment_meets_box(a, b, 4.0 * bx - 0.5, 4.0 * bx + 4.5, 4.0 * by - 0.5, 4.0 * by + 4.5)) continue;
                 const int blk = forest_lookup2(d, bx, by);
                 if (blk >= 0) place(blk);

@@ -576,9 +576,16 @@ __global__ void __launch_bounds__(64) k_links_pass1(DevMesh m, DevLevel d, int32
         // candidate block it of the triangle: box [4bh - h/2, 4(b+1)h + h/2]
         // reached by the block's links, plus a relative margin
         auto centre = [&](int64_t it, int b[3], double c[3]) {
-            b[0] = lo[0] + (int)(it % sx);
-            b[1] = lo[1] + (int)((it / sx) % sy);
-            b[2] = lo[2] + (int)(it / ((int64_t)sx * sy));
+            if (n <= INT32_MAX) {  // 32-bit division where the range allows it
+                const unsigned u = (unsigned)it, usx = (unsigned)sx, q = u / usx;
+                b[0] = lo[0] + (int)(u - q * usx);
+                b[1] = lo[1] + (int)(q % (unsigned)sy);
+                b[2] = lo[2] + (int)(q / (unsigned)sy);
+            } else {
+                b[0] = lo[0] + (int)(it % sx);
+                b[1] = lo[1] + (int)((it / sx) % sy);
+                b[2] = lo[2] + (int)(it / ((int64_t)sx * sy));
+            }
             for (int a = 0; a < 3; a++) c[a] = (b[a] + 0.5) * bw;
         };
         // the first 32 candidates: cheap axes first, into a bit mask, then the
