@@ -13,6 +13,10 @@
 // Where q < 1/2 and the upstream node x - c_p is solid or lies in no block of
 // the level, the link takes simple bounce-back, and is counted: the q >= 1/2
 // form would extrapolate with weight 1 - 1/(2q) -> -infinity as q -> 0.
+//
+// The 26 neighbour blocks come from the level's neighbour table when one is
+// given (built by k_block_nbr, the indices a block-structured solver keeps),
+// else from a walk down the forest.
 #include "geo_internal.h"
 
 namespace {
