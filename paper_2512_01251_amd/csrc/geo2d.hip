@@ -162,12 +162,13 @@ __global__ void __launch_bounds__(256) k2_bins(Dev2Mesh m, Dev2Level d, int kind
         } else {
             const double x0 = fmin(a[0], b[0]) - 0.5, x1 = fmax(a[0], b[0]) + 0.5;
             const double y0 = fmin(a[1], b[1]) - 0.5, y1 = fmax(a[1], b[1]) + 0.5;
-            // blocks whose grown box [4 bx - 1/2, 4 bx + 9/2] can meet [x0, x1] (one
-            // more on the low side, so a box touching only at x0 is tried too)
-            int bx0 = (int)fmin(fmax(floor((x0 - 4.0) / 4.0), -1.0), (double)nbx);
-            int bx1 = (int)fmin(fmax(floor(x1 / 4.0), -1.0), (double)nbx);
-            int by0 = (int)fmin(fmax(floor((y0 - 4.0) / 4.0), -1.0), (double)nby);
-            int by1 = (int)fmin(fmax(floor(y1 / 4.0), -1.0), (double)nby);
+            // blocks whose grown box [4 bx - 1/2, 4 bx + 9/2] meets [x0 + 1/2,
+            // x1 - 1/2]: (x0 - 4) / 4 <= bx <= x1 / 4, closed at both ends (the
+            // roundings are monotone; the 1e-7 only widens the range)
+            int bx0 = (int)fmin(fmax(ceil((x0 - 4.0) / 4.0 - 1e-7), -1.0), (double)nbx);
+            int bx1 = (int)fmin(fmax(floor(x1 / 4.0 + 1e-7), -1.0), (double)nbx);
+            int by0 = (int)fmin(fmax(ceil((y0 - 4.0) / 4.0 - 1e-7), -1.0), (double)nby);
+            int by1 = (int)fmin(fmax(floor(y1 / 4.0 + 1e-7), -1.0), (double)nby);
             if (bx0 < 0) bx0 = 0;
             if (by0 < 0) by0 = 0;
             if (bx1 > nbx - 1) bx1 = nbx - 1;

@@ -451,13 +451,9 @@ __global__ void __launch_bounds__(64) k_rows_pass1(DevMesh m, DevLevel d, int32_
 }
 
 // ------------------------------------------------------------------------
-// LINKS: triangle / widened block box overlap (separating axes, float64,
-// with an outward margin so that rounding can only add candidates)
+// LINKS: triangle / widened block box overlap (separating axes, with outward
+// margins so that rounding can only add candidates)
 // ------------------------------------------------------------------------
-__device__ __forceinline__ bool axis_sep(double p0, double p1, double p2, double r) {
-    const double mn = fmin(p0, fmin(p1, p2)), mx = fmax(p0, fmax(p1, p2));
-    return mn > r || mx < -r;
-}
 
 // Per-triangle quantities of the separating-axis test.
 struct SatTri {
@@ -467,6 +463,7 @@ struct SatTri {
     double nvmin, nvmax;  // min / max over the vertices of n . v
     double nvabs;    // max over the vertices of sum_a |n_a v_a|
     double n1;       // |n|_1
+    float ef[3][3];  // e rounded to float, for the edge axes
 };
 
 __device__ __forceinline__ void sat_setup(SatTri& T) {
@@ -488,15 +485,17 @@ __device__ __forceinline__ void sat_setup(SatTri& T) {
         T.nvabs = fmax(T.nvabs, fabs(T.n[0] * T.v[i][0]) + fabs(T.n[1] * T.v[i][1]) + fabs(T.n[2] * T.v[i][2]));
     }
     T.n1 = fabs(T.n[0]) + fabs(T.n[1]) + fabs(T.n[2]);
+    for (int i = 0; i < 3; i++)
+        for (int a = 0; a < 3; a++) T.ef[i][a] = (float)T.e[i][a];
 }
 
 // Conservative triangle / cube overlap (centre c, half side hs): separating
 // axes are the box normals, the triangle normal and the nine edge crosses,
-// each with a relative margin that covers the rounding of the test.  Stage
-// one takes the box normals and the triangle normal, stage two the edges.
+// each with a margin that covers the rounding of the test.  The box normals
+// are the candidate range itself (the caller enumerates exactly the blocks
+// whose widened box meets the triangle's bounding box); stage one takes the
+// triangle normal, stage two the edges.
 __device__ bool tri_box_stage1(const double c[3], double hs, const SatTri& T) {
-    for (int a = 0; a < 3; a++)
-        if (axis_sep(T.v[0][a] - c[a], T.v[1][a] - c[a], T.v[2][a] - c[a], hs)) return false;
     // the normal axis: projections n . v_i - n . c against the box radius; the
     // margin bounds the rounding of the dot products (4.5 u each side)
     const double nc = T.n[0] * c[0] + T.n[1] * c[1] + T.n[2] * c[2];
@@ -505,25 +504,35 @@ __device__ bool tri_box_stage1(const double c[3], double hs, const SatTri& T) {
     return !(T.nvmin - nc > rn || T.nvmax - nc < -rn);
 }
 
+// The nine edge axes in float.  The vertices relative to the centre,
+// w = v - c, are formed in double and rounded once; |w| is at most the
+// triangle's extent plus the box's, so each projection x1 w1 + x2 w2 carries
+// an absolute error below 4u (|x1| + |x2|) max|w| (u = 2^-24: the roundings
+// of w, of the edge components and of the two products and the sum).  The
+// radius is widened by 1e-6 max|w| (|x1| + |x2|), more than twice that, and
+// by a relative 1e-5 for its own rounding, so an axis is only taken as
+// separating where it separates the exact figures; the 1e-30 floor covers
+// products that underflow.
 __device__ bool tri_box_stage2(const double c[3], double hs, const SatTri& T) {
-    double v0[3], v1[3], v2[3];
-    for (int a = 0; a < 3; a++) {
-        v0[a] = T.v[0][a] - c[a];
-        v1[a] = T.v[1][a] - c[a];
-        v2[a] = T.v[2][a] - c[a];
-    }
-    // nine edge cross axes: axis = e_box(a) x e(i)
+    float w[3][3];
+    float wmax = 0.0f;
+    for (int k = 0; k < 3; k++)
+        for (int a = 0; a < 3; a++) {
+            w[k][a] = (float)(T.v[k][a] - c[a]);
+            wmax = fmaxf(wmax, fabsf(w[k][a]));
+        }
+    const float hsf = (float)hs * (1.0f + 1e-5f) + 1e-6f * wmax + 1e-30f;
+    // axis = e_box(a) x e(i), nonzero in components b1 = a+1 and b2 = a+2
     for (int i = 0; i < 3; i++) {
         for (int a = 0; a < 3; a++) {
-            double ax[3] = {0, 0, 0};
             const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
-            ax[b1] = -T.e[i][b2];
-            ax[b2] = T.e[i][b1];
-            const double p0 = ax[0] * v0[0] + ax[1] * v0[1] + ax[2] * v0[2];
-            const double p1 = ax[0] * v1[0] + ax[1] * v1[1] + ax[2] * v1[2];
-            const double p2 = ax[0] * v2[0] + ax[1] * v2[1] + ax[2] * v2[2];
-            const double r = hs * (fabs(ax[0]) + fabs(ax[1]) + fabs(ax[2]));
-            if (axis_sep(p0, p1, p2, r * (1.0 + 1e-9))) return false;
+            const float x1 = -T.ef[i][b2], x2 = T.ef[i][b1];
+            const float p0 = x1 * w[0][b1] + x2 * w[0][b2];
+            const float p1 = x1 * w[1][b1] + x2 * w[1][b2];
+            const float p2 = x1 * w[2][b1] + x2 * w[2][b2];
+            const float r = hsf * (fabsf(x1) + fabsf(x2));
+            const float mn = fminf(p0, fminf(p1, p2)), mx = fmaxf(p0, fmaxf(p1, p2));
+            if (mn > r || mx < -r) return false;
         }
     }
     return true;
@@ -563,9 +572,12 @@ __global__ void __launch_bounds__(64) k_links_pass1(DevMesh m, DevLevel d, int32
             const int nb[3] = {nbx, nby, nbz};
             for (int a = 0; a < 3; a++) {
                 const double mn = fmin(v[0][a], fmin(v[1][a], v[2][a])), mx = fmax(v[0][a], fmax(v[1][a], v[2][a]));
-                // block b's links reach [4bh - h/2, 4bh + 4.5h]
-                lo[a] = (int)floor((mn - 4.5 * h) / bw);
-                hi[a] = (int)floor((mx + 0.5 * h) / bw);
+                // block b's links reach [4bh - h/2, 4bh + 4.5h]: it meets
+                // [mn, mx] iff (mn - 4.5h) / bw <= b <= (mx + h/2) / bw (the
+                // roundings are monotone and bw is a power of two; the 1e-7
+                // only widens the range)
+                lo[a] = (int)ceil((mn - 4.5 * h) / bw - 1e-7);
+                hi[a] = (int)floor((mx + 0.5 * h) / bw + 1e-7);
                 lo[a] = lo[a] < 0 ? 0 : lo[a];
                 hi[a] = hi[a] > nb[a] - 1 ? nb[a] - 1 : hi[a];
             }
