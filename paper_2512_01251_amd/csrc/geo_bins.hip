@@ -660,13 +660,15 @@ __global__ void k_bins_scatter(const int2* pairs, const int32_t* rank, int64_t c
 }
 
 __global__ void k_check_mesh(DevMesh m, DevLevel d, uint64_t* stats) {
+    // one vertex per thread, its three coordinates in turn (no index division)
     unsigned bad = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)m.nv * 3;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int a = (int)(i % 3);
-        const double x = load_coord(m, (int)(i / 3), a);
-        const bool ok = x == 0.0 || (x >= 0.25 && x <= (double)d.n0[a]);
-        bad += ok ? 0u : 1u;
+    const double top[3] = {(double)d.n0[0], (double)d.n0[1], (double)d.n0[2]};
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < m.nv; v += (int64_t)gridDim.x * blockDim.x) {
+        for (int a = 0; a < 3; a++) {
+            const double x = load_coord(m, (int)v, a);
+            const bool ok = x == 0.0 || (x >= 0.25 && x <= top[a]);
+            bad += ok ? 0u : 1u;
+        }
     }
     wave_count(&stats[GEO_STAT_CONTRACT], bad);
 }
@@ -714,7 +716,7 @@ int launch_bins_scatter(const int2* pairs, const int32_t* rank, int64_t cap, con
 
 int launch_check_mesh(const DevMesh& m, const DevLevel& d, uint64_t* d_stats, hipStream_t s) {
     if (!d_stats || m.nv == 0) return GEO_OK;
-    k_check_mesh<<<grid_for((int64_t)m.nv * 3, 256, 4096), 256, 0, s>>>(m, d, d_stats);
+    k_check_mesh<<<grid_for(m.nv, 256, 4096), 256, 0, s>>>(m, d, d_stats);
     GEO_LAUNCH_CHECK();
     return GEO_OK;
 }
