@@ -1,6 +1,7 @@
-"""bench.py's command line on the host: more than one GPU is refused with a
-message (the multi-GPU sharding is a design, not an implementation), before
-any device is touched."""
+"""bench.py on the host: more than one GPU is refused with a message (the
+multi-GPU sharding is a design, not an implementation), before any device is
+touched; and the HBM traffic figure is taken from the committed counter
+profile only while the kernel it was measured on is unchanged."""
 import os
 import subprocess
 import sys
@@ -14,3 +15,42 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
 
+
+
+def _copy_sources(sources, tmp_path, edit):
+    """Copies of the q kernel's sources, the one named in edit changed."""
+    out = []
+    for p in sources:
+        text = open(p, "rb").read()
+        name = os.path.basename(p)
+        if name in edit:
+            text = edit[name](text)
+        q = tmp_path / name
+        q.write_bytes(text)
+        out.append(str(q))
+    return out
+
+
+def test_traffic_is_taken_only_for_the_profiled_kernel(tmp_path, monkeypatch):
+    """The counter profile names the sha256 of the kernel it was taken on:
+    traffic is reported for that kernel and null once its device code (the
+    kernel file, or the shared header above its host-side declarations)
+    changes; a change to the host-side declarations alone keeps it."""
+    import bench
+    value, note = bench.q_kernel_traffic()
+    assert value is not None and value > 0, note
+
+    marker = b"// host-side launchers"
+    cases = {
+        "kernel": ({"geo_cutlinks.hip": lambda t: t + b"\n// changed\n"}, False),
+        "header device part": ({"geo_internal.h": lambda t: t.replace(marker, b"// changed\n" + marker, 1)}, False),
+        "header host part": ({"geo_internal.h": lambda t: t + b"\n// changed\n"}, True),
+    }
+    sources = list(bench.Q_KERNEL_SOURCES)
+    assert marker in open(sources[1], "rb").read()
+    for name, (edit, kept) in cases.items():
+        d = tmp_path / name.replace(" ", "_")
+        d.mkdir()
+        monkeypatch.setattr(bench, "Q_KERNEL_SOURCES", _copy_sources(sources, d, edit))
+        value, note = bench.q_kernel_traffic()
+        assert (value is not None) == kept, (name, note)
