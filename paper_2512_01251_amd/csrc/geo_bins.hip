@@ -600,37 +600,9 @@ __global__ void __launch_bounds__(64) k_links_pass1(DevMesh m, DevLevel d, int32
             }
             for (int a = 0; a < 3; a++) c[a] = (b[a] + 0.5) * bw;
         };
-        // the first 32 candidates: cheap axes first, into a bit mask, then the
-        // edge axes over the survivors only (the wave iterates as often as
-        // its lane with the most survivors, not with the most candidates)
-        const int n32 = n < 32 ? (int)n : 32;
-        uint32_t pass1 = 0;
-        for (int it = 0; __any(it < n32); it++) {
-            if (it < n32) {
-                int b[3];
-                double c[3];
-                centre(it, b, c);
-                if (tri_box_stage1(c, hs, T)) pass1 |= 1u << it;
-            }
-        }
-        while (__any(pass1 != 0)) {
-            bool has = false;
-            int key = 0;
-            if (pass1) {
-                const int it = __ffs(pass1) - 1;
-                pass1 &= pass1 - 1;
-                int b[3];
-                double c[3];
-                centre(it, b, c);
-                if (tri_box_stage2(c, hs, T)) {
-                    key = forest_lookup(d, b[0], b[1], b[2]);
-                    has = key >= 0;
-                }
-            }
-            app.add(has, key, (int32_t)t);
-        }
-        // candidates beyond the first 32 (large triangles): both stages at once
-        for (int64_t it = 32; __any(it < n); it++) {
+        // every candidate through both stages in turn (a triangle has a few
+        // candidates: its widened box spans one or two blocks per axis)
+        for (int64_t it = 0; __any(it < n); it++) {
             bool has = false;
             int key = 0;
             if (it < n) {
