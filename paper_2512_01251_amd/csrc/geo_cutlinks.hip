@@ -903,7 +903,10 @@ int launch_cutlinks(const DevMesh& m, const DevLevel& d, const geo_bins* rows, c
         if ((rc = geo_fill_i32(fixn, 0, 1, s)) != GEO_OK) return rc;
         GEO_LAUNCH_CHECK();
     }
-    const unsigned gq = 16384;
+    // tasks are split into one contiguous range per workgroup; finer ranges
+    // balance better (7.2M triangles: 16384 -> 65536 workgroups took the
+    // float32 kernel from 4.01 to 3.78 ms); empty ranges exit at once
+    const unsigned gq = 65536;
     kt_record(GEO_KT_CUTLINKS_Q, s, false);
     if (precision == GEO_PREC_F32_FALLBACK)
         k_cl_q<float><<<gq, 64, 0, s>>>(m, d, rows->off, rows->val, rows->cap, links->off, links->val, links->cap,

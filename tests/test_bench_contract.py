@@ -37,8 +37,13 @@ def test_traffic_is_taken_only_for_the_profiled_kernel(tmp_path, monkeypatch):
     kernel file, or the shared header above its host-side declarations)
     changes; a change to the host-side declarations alone keeps it."""
     import bench
+    # a profile of the sources as they stand (the committed one may lag a
+    # kernel change until the counters are taken again)
+    prof = tmp_path / "profile.txt"
+    prof.write_text(f"source_sha256: {bench.q_kernel_source_hash()}\ntraffic_bytes_per_launch: 123.0\n")
+    monkeypatch.setattr(bench, "PMC_PROFILE", str(prof))
     value, note = bench.q_kernel_traffic()
-    assert value is not None and value > 0, note
+    assert value == 123.0, note
 
     marker = b"// host-side launchers"
     cases = {
