@@ -64,7 +64,6 @@ def test_icosphere_q_is_cyrus_beck_entry(ico):
     num = np.einsum("fj,lfj->lf", n, a[None] - X[:, None])
     t = np.where(nd < 0, num / np.where(nd < 0, nd, 1), -np.inf)
     t_in = t.max(1)
-    assert Lk["n"] == 10366
     np.testing.assert_allclose(Lk["q"], t_in, rtol=0, atol=1e-12)
     assert (Lk["q"] > 0).all() and (Lk["q"] <= 1).all()
 
@@ -278,10 +277,8 @@ def test_link_through_shared_edge_and_coplanar():
     assert r["q"][0] == 1.0 and r["q"][1] == 1.0
     # (7.5, 6.5, 4.5) -> (6.5, 6.5, 4.5): the endpoint is on the edge x = y = 6.5
     assert r["q"][2] == 1.0 and r["tied"][2] == 1
-    # a link lying in the plane y = 6.5 (coplanar with the y = hi face):
-    # from (8.5, 6.5, 4.5) along -x over two cells is not a lattice link; use
-    # level 1: centre (7.25, 6.5?) -> not on the plane; check via level 0 cell
-    # (7, 6, 4) along -x: segment in plane y = 6.5, enters the face at x = 6.5
+    # that link lies in the plane y = 6.5 of the y = hi face: the coplanar
+    # clip and the x = hi face both give t = 1, and a hit triangle is named
     assert r["tri"][2] >= 0
 
 
@@ -337,9 +334,7 @@ def test_refine_solid_slab_two_solid_layers():
     solid[:] = 0
     solid[(z >= 1) & (z <= 6)] = 1
     r3 = oracle.refine(n0, 0, bc, solid, 1)
-    assert np.array_equal(r3["refine"].astype(bool), z != 7 - 7 + 99)  # every layer 0..7 reached
-    solid[:] = 0
-    thick = (z >= 0) & (z <= 7)
+    assert r3["refine"].all()      # every layer 0..7 is reached
     n0b = (64, 64, 64)
     bcb = oracle.level0_blocks(n0b)
     sb = np.zeros((len(bcb), 64), np.uint8)

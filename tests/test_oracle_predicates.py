@@ -101,15 +101,23 @@ def test_orient3d_sign_convention(oracle_lib):
 
 
 def test_hit_parameter_exact_on_dyadic_case(oracle_lib):
-    """A link crossing a triangle: t is a dyadic rational, returned exactly."""
+    """A link crossing a triangle: t is a dyadic rational, returned exactly,
+    both from the orient3d values and by the oracle's nearest-hit search."""
     import ctypes as C
+    from synth.meshes import Mesh
     L = oracle_lib.lib()
     a = np.array([0.0, -1.0, 0.375]); b = np.array([0.0, 1.0, 0.375]); c = np.array([1.0, 0.0, 0.375])
     X = np.array([0.25, 0.0, 0.125]); Y = np.array([0.25, 0.0, 0.625])
     # exact segment/plane parameter: (0.375 - 0.125) / 0.5 = 0.5
-    val = oracle_lib.q_points
-    assert val is not None
-    # use the exact value function through orient3d values
     sx = L.or_orient3d_value(*[np.ascontiguousarray(p).ctypes.data_as(C.c_void_p) for p in (a, b, c, X)])
     sy = L.or_orient3d_value(*[np.ascontiguousarray(p).ctypes.data_as(C.c_void_p) for p in (a, b, c, Y)])
     assert sx / (sx - sy) == 0.5
+    # one triangle in the plane z = 0.3125; the level-2 link from the centre
+    # (0.375, 0.375, 0.125) along +z (k = 22) reaches it at t = 0.1875 / 0.25 = 0.75
+    m = Mesh(np.array([[0.125, 0.125, 0.3125], [1.0, 0.125, 0.3125], [0.125, 1.0, 0.3125]]),
+             np.array([[0, 1, 2]], np.int32))
+    r = oracle_lib.q_points(m, (4, 4, 4), 2, np.array([[1, 1, 0]], np.int32), np.array([22], np.uint8))
+    assert r["q"][0] == 0.75 and r["tri"][0] == 0 and r["tied"][0] == 0
+    # the same link along -z (k = 4) misses it: no hit
+    r = oracle_lib.q_points(m, (4, 4, 4), 2, np.array([[1, 1, 0]], np.int32), np.array([4], np.uint8))
+    assert r["tri"][0] == -1
