@@ -75,7 +75,8 @@ def lib():
         L.or_links.argtypes = [P, P, i32, P, i32, i64, P, i32, i64, P, P, P, P, P, P]
         L.or_links.restype = i64
         L.or_q_points.argtypes = [P, P, i32, P, i32, i64, P, P, P, P, P]
-        L.or_grad.argtypes = [P, P, i32, P, i32, i64, P, i64, P, P, P, P, P]
+        L.or_grad.argtypes = [P, P, i32, P, i32, i64, P, i64, P, P, P, P, i32, P]
+        L.or_q_given.argtypes = [P, P, i32, P, i32, i64, P, P, P, P, P]
         L.or_num_threads.restype = i32
         L.or2_solid_point.argtypes = [P, P, P, i32, P]
         L.or2_classify_blocks.argtypes = [P, P, i32, P, i32, i64, P, i32, P]
@@ -236,7 +237,28 @@ def q_points(mesh, n0, L: int, cells: np.ndarray, dirs: np.ndarray) -> dict:
     return {"q": q, "tri": tri, "tied": tied}
 
 
-def grad(mesh, n0, L: int, bcoord: np.ndarray, link_cell, link_dir, link_tri, w) -> np.ndarray:
+def q_given(mesh, n0, L: int, cells: np.ndarray, dirs: np.ndarray, tris: np.ndarray) -> dict:
+    """For links given by cell index triples and directions, and a triangle
+    named for each: the exact hit parameter of that triangle along the link
+    (-1 if the closed segment misses it) and whether it equals the nearest
+    hit exactly (the named triangle is one of the minimisers)."""
+    V, T = _mesh_arrays(mesh)
+    cells = np.ascontiguousarray(cells, dtype=np.int32).reshape(-1, 3)
+    dirs = np.ascontiguousarray(dirs, dtype=np.uint8)
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    n = len(cells)
+    q = np.zeros(n, np.float64)
+    is_min = np.zeros(n, np.uint8)
+    n0a = np.ascontiguousarray(n0, dtype=np.int32)
+    lib().or_q_given(_p(V), _p(T), T.shape[0], _p(n0a), L, n, _p(cells), _p(dirs), _p(tris), _p(q), _p(is_min))
+    return {"q": q, "is_min": is_min.astype(bool)}
+
+
+def grad(mesh, n0, L: int, bcoord: np.ndarray, link_cell, link_dir, link_tri, w,
+         absolute: bool = False) -> np.ndarray:
+    """dL/dv for L = sum_i w_i q_i (closed form, see or_grad).  absolute=True
+    sums |w_i| |dq_i/dv| instead: per component, the scale G_abs against which
+    a float32 scatter-add of the same terms is judged."""
     V, T = _mesh_arrays(mesh)
     bc = np.ascontiguousarray(bcoord, dtype=np.int32)
     lc = np.ascontiguousarray(link_cell, dtype=np.int32)
@@ -246,7 +268,7 @@ def grad(mesh, n0, L: int, bcoord: np.ndarray, link_cell, link_dir, link_tri, w)
     g = np.zeros((V.shape[0], 3), np.float64)
     n0a = np.ascontiguousarray(n0, dtype=np.int32)
     lib().or_grad(_p(V), _p(T), V.shape[0], _p(n0a), L, len(bc), _p(bc), len(lc), _p(lc), _p(ld),
-                  _p(lt), _p(ww), _p(g))
+                  _p(lt), _p(ww), 1 if absolute else 0, _p(g))
     return g
 
 

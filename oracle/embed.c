@@ -572,14 +572,67 @@ void or_q_points(const double* V, const int32_t* T, int nt, const int32_t* n0, i
     buckets_free(&B);
 }
 
+/* For explicitly given links and a triangle named for each: the exact hit
+ * parameter of that triangle along the link (-1 when the closed segment
+ * misses it), and whether that parameter equals the nearest hit exactly
+ * (the named triangle is one of the minimisers).  Checks a hit triangle
+ * chosen elsewhere without asking it to be the smallest index at ties. */
+void or_q_given(const double* V, const int32_t* T, int nt, const int32_t* n0, int L, int64_t n,
+                const int32_t* cell, const uint8_t* dir, const int32_t* given, double* given_q,
+                uint8_t* given_is_min) {
+    buckets B;
+    buckets_build(&B, 3, V, T, nt, n0);
+    double h = ldexp(1.0, -L);
+#pragma omp parallel
+    {
+        int32_t* buf = NULL;
+        int bcap = 0;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < n; i++) {
+            int cv[3];
+            dir_vec(dir[i], cv);
+            double X[3], Y[3], lo[3], hi[3];
+            for (int a = 0; a < 3; a++) {
+                X[a] = centre(cell[3 * i + a], L);
+                Y[a] = X[a] + cv[a] * h;
+                lo[a] = fmin(X[a], Y[a]);
+                hi[a] = fmax(X[a], Y[a]);
+            }
+            given_q[i] = -1.0;
+            given_is_min[i] = 0;
+            int g = given[i];
+            if (g < 0 || g >= nt) continue;
+            const double *a = V3(V, T[3 * g]), *b = V3(V, T[3 * g + 1]), *c = V3(V, T[3 * g + 2]);
+            or_hit hg;
+            if (!or_segment_hit(a, b, c, X, Y, &hg)) continue;
+            given_q[i] = or_hit_value(&hg);
+            /* the nearest hit over the link's candidates */
+            int m = box_candidates(&B, V, T, lo, hi, &buf, &bcap);
+            int below = 0;
+            for (int j = 0; j < m && !below; j++) {
+                int t = buf[j];
+                or_hit hj;
+                const double *ta = V3(V, T[3 * t]), *tb = V3(V, T[3 * t + 1]), *tc = V3(V, T[3 * t + 2]);
+                if (or_segment_hit(ta, tb, tc, X, Y, &hj) && or_hit_cmp(&hj, &hg) < 0) below = 1;
+            }
+            given_is_min[i] = (uint8_t)!below;
+        }
+        free(buf);
+    }
+    buckets_free(&B);
+}
+
 /* ------------------------------------------------------------------------- */
 /* gradient of L = sum_i w_i q_i with respect to the vertices                 */
 /* dq/dv_j = lambda_j n / (n . d)  (hit point barycentrics lambda)            */
 /* ------------------------------------------------------------------------- */
 
+/* absolute = 1: the same sum with every term replaced by its magnitude,
+ * |w_i| |lambda_j n_a / (n . d)| (the scale of the sum's rounding). */
 void or_grad(const double* V, const int32_t* T, int nv, const int32_t* n0, int L, int64_t nb,
              const int32_t* bcoord, int64_t nlinks, const int32_t* link_cell,
-             const uint8_t* link_dir, const int32_t* link_tri, const double* w, double* grad) {
+             const uint8_t* link_dir, const int32_t* link_tri, const double* w, int absolute,
+             double* grad) {
     (void)n0; (void)nb;
     memset(grad, 0, sizeof(double) * 3 * (size_t)nv);
     double h = ldexp(1.0, -L);
@@ -616,7 +669,10 @@ void or_grad(const double* V, const int32_t* T, int nv, const int32_t* n0, int L
             lam[j] = (n[0] * cr[0] + n[1] * cr[1] + n[2] * cr[2]) / nn;
         }
         for (int j = 0; j < 3; j++)
-            for (int a_ = 0; a_ < 3; a_++) grad[3 * (int64_t)tv[j] + a_] += w[i] * lam[j] * n[a_] / nd;
+            for (int a_ = 0; a_ < 3; a_++) {
+                double term = w[i] * lam[j] * n[a_] / nd;
+                grad[3 * (int64_t)tv[j] + a_] += absolute ? fabs(term) : term;
+            }
     }
 }
 

@@ -15,7 +15,7 @@ from dataclasses import dataclass, field
 import torch
 
 from . import (GEO_BINS_LINKS, GEO_BINS_ROWS, GEO_CALL_BINS_LINKS, GEO_CALL_BINS_ROWS, GEO_CALL_CUTLINKS,
-               GEO_CALL_LINKS_DENSE, GEO_CALL_REFINE, GEO_NSTATS, GEO_PREC_F32_FALLBACK, GEO_PREC_F64,
+               GEO_CALL_LINKS_DENSE, GEO_CALL_REFINE, GEO_NSTATS, GEO_STAT_CONTRACT, GEO_PREC_F32_FALLBACK, GEO_PREC_F64,
                geo_build_bins, geo_cutlinks, geo_cutlinks_backward, geo_level0_blocks, geo_links_dense, geo_nprop,
                geo_refine_flags, geo_solid_change, geo_voxelize, geo_workspace_size, make_bins, make_level,
                make_mesh)
@@ -86,15 +86,21 @@ class Embedder:
     # -- the path ----------------------------------------------------------------
     def embed(self, verts: torch.Tensor, tris: torch.Tensor, n0, lf: int, lattice: int,
               d_spec: float = 2.0, precision: str = "f32", with_links: bool = True,
-              with_mask: bool = False) -> Embedding:
+              with_mask: bool = False, check_contract: bool = True) -> Embedding:
+        """Embeds the mesh (levels 0..lf, then the cut links of level lf).
+        Raises ValueError when a vertex coordinate breaks the coordinate
+        range of the library (the results would be unspecified), unless
+        check_contract is False; the violation count is then in stats."""
         # each pass sizes at least the first level whose buffers overflowed
         for _ in range(lf + 4):
-            out = self._embed_once(verts, tris, n0, lf, lattice, d_spec, precision, with_links, with_mask)
+            out = self._embed_once(verts, tris, n0, lf, lattice, d_spec, precision, with_links, with_mask,
+                                   check_contract)
             if out is not None:
                 return out
         raise RuntimeError("buffer capacities did not converge")
 
-    def _embed_once(self, verts, tris, n0, lf, lattice, d_spec, precision, with_links, with_mask):
+    def _embed_once(self, verts, tris, n0, lf, lattice, d_spec, precision, with_links, with_mask,
+                    check_contract=True):
         """One pass over all levels.  Bin and link counts are checked once, at
         the end: every kernel clamps to the capacity it is given, so a pass that
         overflowed a buffer is memory-safe and is simply redone with larger
@@ -160,8 +166,12 @@ class Embedder:
         if with_links:
             out.links = self._cutlinks(mesh, n0, lf, out.levels[-1], child_maps, rows, lattice, prec, stats,
                                        with_mask, cnt(2 * lf + 1), cnt(2 * lf + 2), checks)
-        # the final wait: every count at once
-        counts = ctr[GEO_NSTATS:].cpu().tolist()
+        # the final wait: every count and statistic at once
+        allc = ctr.cpu().tolist()
+        if check_contract and allc[GEO_STAT_CONTRACT]:
+            raise ValueError(f"{allc[GEO_STAT_CONTRACT]} vertex coordinates lie outside the library's coordinate "
+                             "range (each coordinate must be 0 or in [1/4, n0], finite); the results are unspecified")
+        counts = allc[GEO_NSTATS:]
         if with_links and counts[2 * lf + 2] > 2 ** 31 - 1:
             raise RuntimeError(f"{counts[2 * lf + 2]} links exceed the table's int32 offsets")
         ok = True

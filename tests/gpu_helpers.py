@@ -22,11 +22,13 @@ def to_gpu(mesh):
     return V, T
 
 
-def gpu_embed(w, precision, with_links=True):
+def gpu_embed(w, precision, with_links=True, with_mask=None, check_contract=True):
     from paper_2512_01251_amd import pipeline
     V, T = to_gpu(w.mesh)
+    if with_mask is None:
+        with_mask = with_links and w.mesh.nt < 500000
     emb = pipeline.Embedder().embed(V, T, w.n0, w.lf, w.lattice, w.d_spec, precision, with_links,
-                                    with_mask=with_links and w.mesh.nt < 500000)
+                                    with_mask=with_links and with_mask, check_contract=check_contract)
     return emb, V, T
 
 

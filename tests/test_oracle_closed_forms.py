@@ -342,3 +342,94 @@ def test_parity_agrees_along_all_axes(name):
         total += int(clear.sum())
         assert 0.1 < got.mean() < 0.9
     assert total > 6 * 14000
+
+
+# ----------------------------------------------------------------------------
+# hit parameter of a named triangle; the gradient's absolute-term scale
+# ----------------------------------------------------------------------------
+
+def test_q_given_on_three_crossings():
+    """A thin slab x in [2.75, 3.0] and a box x in [3.25, 6.0] (both spanning
+    y, z in [2.25, 6.75]): the level-0 link from (2.5, 3.5, 4.5) along +x (a
+    fluid centre to the solid centre (3.5, 3.5, 4.5)) crosses the slab's two
+    x faces at t = 1/4 and 1/2 and the box's low x face at t = 3/4, all
+    dyadic, so the hit parameters are exact.  A triangle of each face named
+    for the link gets its own t; only the slab's low face is a minimiser; a
+    y face (never met) gets -1.  The oracle's own nearest triangles of the
+    icosphere table are minimisers at the table's q.
+    Slips caught: the named triangle's t taken from the nearest hit, is_min
+    with the comparison reversed, a miss reported as t = 0."""
+    slab = meshes.box((2.75, 2.25, 2.25), (3.0, 6.75, 6.75))
+    body = meshes.box((3.25, 2.25, 2.25), (6.0, 6.75, 6.75))
+    py, pz = 3.5, 4.5
+    m = meshes.merge([slab, body])
+    meshes.check_closed_oriented(m)
+    V, T = m.verts.astype(np.float64), m.tris
+    a = V[T[:, 0]]
+    n = np.cross(V[T[:, 1]] - a, V[T[:, 2]] - a)
+    xface = np.abs(n[:, 0]) > 0
+    # (y, z) = (3.5, 4.5) lies on neither diagonal of these faces: one
+    # triangle of each x face contains the crossing point; find it by the 2D
+    # point-in-triangle test on (y, z)
+    def holder(x0):
+        for t in np.nonzero(xface & np.isclose(a[:, 0], x0))[0]:
+            P = V[T[t]][:, 1:]
+            d = np.array([(P[(i + 1) % 3][0] - P[i][0]) * (pz - P[i][1])
+                          - (P[(i + 1) % 3][1] - P[i][1]) * (py - P[i][0]) for i in range(3)])
+            if (d > 0).all() or (d < 0).all():
+                return t
+        raise AssertionError(x0)
+    t_lo, t_hi, t_body = holder(2.75), holder(3.0), holder(3.25)
+    yface = np.nonzero(np.abs(n[:, 1]) > 0)[0][0]
+    cells = np.array([[2, 3, 4]] * 4, np.int32)
+    dirs = np.array([14] * 4, np.uint8)          # c = (+1, 0, 0)
+    r = oracle.q_given(m, (12, 12, 12), 0, cells, dirs, np.array([t_lo, t_hi, t_body, yface], np.int32))
+    assert r["q"].tolist() == [0.25, 0.5, 0.75, -1.0]
+    assert r["is_min"].tolist() == [True, False, False, False]
+    near = oracle.q_points(m, (12, 12, 12), 0, cells[:1], dirs[:1])
+    assert near["q"][0] == 0.25 and near["tri"][0] == t_lo
+    w = configs.icosphere64()
+    ref = oracle.embed(w.mesh, w.n0, w.lf, 19)
+    Lk, lv = ref["links"], ref["levels"][-1]
+    t = Lk["cell"] % 64
+    cells = 4 * lv["bcoord"][Lk["cell"] // 64] + np.stack([t & 3, (t >> 2) & 3, t >> 4], 1)
+    g = oracle.q_given(w.mesh, w.n0, 0, cells, Lk["dir"], Lk["tri"])
+    assert np.array_equal(g["q"], Lk["q"]) and g["is_min"].all()
+
+
+def test_grad_absolute_sums_to_the_translation_scale():
+    """For one link with weight w and a hit inside its triangle (barycentrics
+    lambda_j >= 0, summing to 1), the absolute-term gradient summed over the
+    triangle's three vertices is |w| |n_a| / |n . d| per component (the
+    signed sum is w n / (n . d), translation invariance).  With the weights of
+    all links negated the absolute form is unchanged and the signed form
+    flips.  Slips caught: abs taken of the summed gradient instead of each
+    term, the weight's sign kept, a vertex's term dropped."""
+    w = configs.icosphere64()
+    ref = oracle.embed(w.mesh, w.n0, w.lf, 19)
+    Lk, lv = ref["links"], ref["levels"][-1]
+    ok = np.nonzero((Lk["tied"] == 0) & (Lk["q"] > 0.05) & (Lk["q"] < 0.95))[0]
+    rng = np.random.default_rng(7)
+    D = _dirs()
+    for i in rng.choice(ok, 12, replace=False):
+        wv = np.zeros(Lk["n"])
+        wv[i] = -0.625
+        ga = oracle.grad(w.mesh, w.n0, 0, lv["bcoord"], Lk["cell"], Lk["dir"], Lk["tri"], wv, absolute=True)
+        gs = oracle.grad(w.mesh, w.n0, 0, lv["bcoord"], Lk["cell"], Lk["dir"], Lk["tri"], wv)
+        vt = w.mesh.tris[Lk["tri"][i]]
+        a, b, c = w.mesh.verts[vt]
+        n = np.cross(b - a, c - a)
+        d = D[Lk["dir"][i]].astype(np.float64)
+        np.testing.assert_allclose(ga[vt].sum(0), 0.625 * np.abs(n) / abs(n.dot(d)), rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(gs[vt].sum(0), -0.625 * n / n.dot(d), rtol=1e-12, atol=1e-15)
+        assert (ga >= np.abs(gs) - 1e-15).all()
+        others = np.setdiff1d(np.arange(len(ga)), vt)
+        assert (ga[others] == 0).all()
+    wv = rng.uniform(-1, 1, Lk["n"])
+    ga = oracle.grad(w.mesh, w.n0, 0, lv["bcoord"], Lk["cell"], Lk["dir"], Lk["tri"], wv, absolute=True)
+    gn = oracle.grad(w.mesh, w.n0, 0, lv["bcoord"], Lk["cell"], Lk["dir"], Lk["tri"], -wv, absolute=True)
+    gs = oracle.grad(w.mesh, w.n0, 0, lv["bcoord"], Lk["cell"], Lk["dir"], Lk["tri"], wv)
+    gsn = oracle.grad(w.mesh, w.n0, 0, lv["bcoord"], Lk["cell"], Lk["dir"], Lk["tri"], -wv)
+    assert np.array_equal(ga, gn)
+    np.testing.assert_allclose(gsn, -gs, rtol=0, atol=1e-12)
+    assert (ga >= np.abs(gs) - 1e-12).all()
