@@ -1,13 +1,22 @@
 """GPU parity at the full benchmark sizes.
 
-star112k (112,000 triangles, 128^3 base, levels 0..3, D3Q19): the whole
-forest is compared with the oracle (every cell of every level, classes,
-marks, child maps); links on a random sample.
+star112k (112,000 triangles, 128^3 base, levels 0..3, D3Q19) and spheres64
+(1,024,000 triangles, 256^3 base, levels 0..3, D3Q19): the whole forest
+(every cell of every level, classes, marks, child maps) and the whole link
+set of the finest level (the link mask of every cell, the link count, the
+table's (cell, direction) order) against the oracle; q and the hit triangle
+on a random sample of links.
 
 star7m (7,200,000 triangles, float32 vertices, 256^3 base, levels 0..4,
-D3Q27; the benchmark workload in the benchmark's launch configuration):
-sampled cells and links against the oracle's point functions, and
+D3Q27; the benchmark workload in the benchmark's launch configuration): the
+whole forest and the whole link set in both forms; the oracle's own link
+table (mask, cells, directions, q, hit triangles) on a sample of blocks that
+includes blocks with no link-bin candidates; q on a random sample of links;
 invariants that hold at any size.
+
+The whole link set comes from the oracle's solid flags of the level and the
+oracle's point rule for neighbour centres in no block (link_sets.py), so a
+link or a block the GPU drops is found.
 """
 import numpy as np
 import pytest
@@ -15,15 +24,50 @@ import pytest
 import oracle
 from synth import configs
 from gpu_helpers import gpu_embed, say
+from link_sets import level_link_set
 
 pytestmark = pytest.mark.gpu
+
+Q_TOL = 1e-5
 
 
 def _cells_of(bcoord, blocks, t):
     return 4 * bcoord[blocks] + np.stack([t & 3, (t >> 2) & 3, t >> 4], 1)
 
 
+def _check_forest(emb, ref):
+    assert len(emb.levels) == len(ref["levels"])
+    for g, r in zip(emb.levels, ref["levels"]):
+        L = r["level"]
+        assert np.array_equal(g.bcoord.cpu().numpy(), r["bcoord"]), f"blocks L{L}"
+        gs = g.solid.cpu().numpy().view(np.uint64)
+        assert np.array_equal(gs, r["solid"]), f"solid L{L}: {np.count_nonzero(gs != r['solid'])} blocks differ"
+        if "refine" in r:
+            assert np.array_equal(g.bclass.cpu().numpy(), r["bclass"]), f"bclass L{L}"
+            assert np.array_equal(g.refine.cpu().numpy(), r["refine"]), f"refine L{L}"
+            assert np.array_equal(g.child_map.cpu().numpy(), r["child_map"]), f"child_map L{L}"
+
+
+def _check_link_set(emb, lset):
+    """Every link of the level: count, (cell, direction) in table order, and
+    the mask of every cell when the GPU wrote it."""
+    Lk = emb.links
+    n_ref = len(lset["cell"])
+    assert Lk.n == n_ref, (Lk.n, n_ref)
+    assert np.array_equal(Lk.cell.cpu().numpy().astype(np.int64), lset["cell"]), "link cells"
+    assert np.array_equal(Lk.dir.cpu().numpy(), lset["dir"]), "link directions"
+    if Lk.mask is not None:
+        nb = int(emb.levels[-1].bcoord.shape[0])
+        full = np.zeros((nb, 64), np.uint32)
+        full[lset["blocks"]] = lset["masks"]
+        gm = Lk.mask.cpu().numpy().view(np.uint32).reshape(nb, 64)
+        assert np.array_equal(gm, full), f"link mask: {np.count_nonzero(gm != full)} cells differ"
+
+
 def _check_links_sample(w, emb, rng, n):
+    """q and hit triangle of n random links against the oracle's nearest hit;
+    where the oracle finds several triangles at the minimum, the GPU's must
+    be one of them."""
     lv = emb.levels[-1]
     L = lv.level
     bc = lv.bcoord.cpu().numpy()
@@ -35,31 +79,56 @@ def _check_links_sample(w, emb, rng, n):
     ref = oracle.q_points(w.mesh, w.n0, L, cells, dirs)
     q = Lk.q.cpu().numpy()[idx].astype(np.float64)
     err = np.abs(q - ref["q"])
-    assert err.max() <= 1e-5, err.max()
+    assert err.max() <= Q_TOL, err.max()
     tri = Lk.tri.cpu().numpy()[idx]
     untied = ref["tied"] == 0
     assert np.array_equal(tri[untied], ref["tri"][untied])
-    # the link joins a fluid centre to a solid one
-    c = np.array([[k % 3 - 1, (k // 3) % 3 - 1, k // 9 - 1] for k in range(27)])
-    X = (cells + 0.5) * 2.0 ** -L
-    Y = (cells + c[dirs] + 0.5) * 2.0 ** -L
-    assert not oracle.solid_points(w.mesh, w.n0, X).any()
-    assert oracle.solid_points(w.mesh, w.n0, Y).all()
-    return float(err.max())
+    tied = np.nonzero(~untied)[0]
+    if len(tied):
+        g = oracle.q_given(w.mesh, w.n0, L, cells[tied], dirs[tied], tri[tied])
+        assert g["is_min"].all(), f"{np.count_nonzero(~g['is_min'])} tied links name a triangle off the minimum"
+    return float(err.max()), len(tied)
 
 
-def _check_cells_sample(w, emb, rng, n):
-    for lv in emb.levels:
-        bc = lv.bcoord.cpu().numpy()
-        solid = lv.solid.cpu().numpy().view(np.uint64)
-        mixed = np.nonzero((solid != 0) & (solid != np.uint64(0xFFFFFFFFFFFFFFFF)))[0]
-        b = np.concatenate([rng.integers(0, len(bc), n // 2),
-                            mixed[rng.integers(0, len(mixed), n // 2)] if len(mixed) else []]).astype(np.int64)
-        t = rng.integers(0, 64, len(b))
-        cells = _cells_of(bc, b, t)
-        ref = oracle.solid_points(w.mesh, w.n0, (cells + 0.5) * 2.0 ** -lv.level)
-        got = ((solid[b] >> t.astype(np.uint64)) & np.uint64(1)).astype(np.uint8)
-        assert np.array_equal(got, ref), f"level {lv.level}: {np.count_nonzero(got != ref)} of {len(b)}"
+def _check_block_sample(w, emb, lset, rng, n_link_blocks, n_random, n_empty_bins):
+    """The oracle's whole link table (mask, cells, directions, q, triangles)
+    on a sample of blocks: blocks with links, random blocks, and candidate
+    blocks (a fluid cell near a solid one) whose link bins are empty."""
+    lv = emb.levels[-1]
+    L = lv.level
+    bc = lv.bcoord.cpu().numpy()
+    nb = len(bc)
+    gcell = emb.links.cell.cpu().numpy().astype(np.int64)
+    gblk = gcell // 64
+    with_links = np.unique(gblk)
+    boff = emb.links.bins_off.cpu().numpy().astype(np.int64)
+    empty = np.nonzero(boff[1:nb + 1] == boff[:nb])[0]
+    empty_cand = np.intersect1d(empty, lset["blocks"])
+    pick = [rng.choice(with_links, min(n_link_blocks, len(with_links)), replace=False),
+            rng.choice(nb, min(n_random, nb), replace=False)]
+    if len(empty_cand):
+        pick.append(rng.choice(empty_cand, min(n_empty_bins, len(empty_cand)), replace=False))
+    sel = np.unique(np.concatenate(pick))
+    ref = oracle.links(w.mesh, w.n0, L, bc[sel], w.lattice)
+    # the GPU's table restricted to the sampled blocks, in the same order
+    lo = np.searchsorted(gblk, sel, side="left")
+    hi = np.searchsorted(gblk, sel, side="right")
+    rows = np.concatenate([np.arange(a, b) for a, b in zip(lo, hi)]) if len(sel) else np.zeros(0, np.int64)
+    pos_in_sel = np.repeat(np.arange(len(sel)), hi - lo)
+    got_cell = pos_in_sel * 64 + gcell[rows] % 64
+    assert len(rows) == ref["n"], (len(rows), ref["n"])
+    assert np.array_equal(got_cell, ref["cell"].astype(np.int64))
+    assert np.array_equal(emb.links.dir.cpu().numpy()[rows], ref["dir"])
+    q = emb.links.q.cpu().numpy()[rows].astype(np.float64)
+    err = np.abs(q - ref["q"]) if ref["n"] else np.zeros(1)
+    assert err.max() <= Q_TOL, err.max()
+    untied = ref["tied"] == 0
+    assert np.array_equal(emb.links.tri.cpu().numpy()[rows][untied], ref["tri"][untied])
+    if emb.links.mask is not None:
+        gm = emb.links.mask.cpu().numpy().view(np.uint32).reshape(nb, 64)[sel]
+        assert np.array_equal(gm, ref["mask"])
+    return {"blocks": len(sel), "empty_bin_candidates": int(len(empty_cand)), "links": int(ref["n"]),
+            "max_dq": float(err.max())}
 
 
 def _check_invariants(w, emb):
@@ -96,51 +165,56 @@ def _check_invariants(w, emb):
     assert (np.diff(key) > 0).all()
 
 
+def _forest_and_links(w):
+    say(f"[fullsize] {w.name}: oracle forest ...")
+    ref = oracle.embed(w.mesh, w.n0, w.lf, w.lattice, w.d_spec, with_links=False)
+    lv = ref["levels"][-1]
+    say(f"[fullsize] {w.name}: link set from the oracle's flags ...")
+    lset = level_link_set(w.mesh, w.n0, w.lf, lv["bcoord"], lv["solid"], w.lattice)
+    say(f"[fullsize] {w.name}: {len(lset['cell'])} links in {len(lset['blocks'])} candidate blocks")
+    return w, ref, lset
+
+
 @pytest.fixture(scope="module")
 def c1():
-    w = configs.star112k()
-    say("[fullsize] star112k oracle forest ...")
-    ref = oracle.embed(w.mesh, w.n0, w.lf, w.lattice, w.d_spec, with_links=False)
-    return w, ref
+    return _forest_and_links(configs.star112k())
 
 
 @pytest.mark.parametrize("precision", ["f32", "f64"])
-def test_star112k_forest_exact_and_links_sampled(c1, precision):
-    w, ref = c1
+def test_star112k_forest_and_link_set(c1, precision):
+    w, ref, lset = c1
     say(f"[fullsize] star112k {precision}")
-    emb, _, _ = gpu_embed(w, precision)
-    for g, r in zip(emb.levels, ref["levels"]):
-        assert np.array_equal(g.bcoord.cpu().numpy(), r["bcoord"])
-        assert np.array_equal(g.solid.cpu().numpy().view(np.uint64), r["solid"]), f"solid L{r['level']}"
-        if "refine" in r:
-            assert np.array_equal(g.bclass.cpu().numpy(), r["bclass"])
-            assert np.array_equal(g.refine.cpu().numpy(), r["refine"])
-            assert np.array_equal(g.child_map.cpu().numpy(), r["child_map"])
+    emb, _, _ = gpu_embed(w, precision, with_mask=True)
+    _check_forest(emb, ref)
+    _check_link_set(emb, lset)
     _check_invariants(w, emb)
-    e = _check_links_sample(w, emb, np.random.default_rng(1), 20000)
-    say(f"[fullsize] star112k {precision} ok: {emb.links.n} links, sampled max |dq| {e:.2e}")
+    e, nt = _check_links_sample(w, emb, np.random.default_rng(1), 20000)
+    say(f"[fullsize] star112k {precision} ok: {emb.links.n} links, sampled max |dq| {e:.2e}, {nt} tied")
 
 
 @pytest.fixture(scope="module")
 def c2():
-    return configs.star7m()
+    return _forest_and_links(configs.star7m())
 
 
 @pytest.mark.parametrize("precision", ["f32", "f64"])
-def test_star7m_sampled(c2, precision):
-    w = c2
+def test_star7m_forest_and_link_set(c2, precision):
+    w, ref, lset = c2
     say(f"[fullsize] star7m {precision}")
     emb, _, _ = gpu_embed(w, precision)
-    rng = np.random.default_rng(2)
+    _check_forest(emb, ref)
+    _check_link_set(emb, lset)
     _check_invariants(w, emb)
-    _check_cells_sample(w, emb, rng, 4000)
-    e = _check_links_sample(w, emb, rng, 3000)
+    rng = np.random.default_rng(2)
+    bs = _check_block_sample(w, emb, lset, rng, 4000, 2000, 1000)
+    e, nt = _check_links_sample(w, emb, rng, 20000)
     st = emb.stats.cpu().numpy()
-    say(f"[fullsize] star7m {precision} ok: {emb.links.n} links, sampled max |dq| {e:.2e}, stats {st.tolist()}")
+    say(f"[fullsize] star7m {precision} ok: {emb.links.n} links, block sample {bs}, sampled max |dq| {e:.2e}, "
+        f"{nt} tied, stats {st.tolist()}")
     assert st[3] == 0
 
 
-def test_star7m_bounce_back_properties(c2):
+def test_star7m_bounce_back_properties():
     """Bounce-back over every link of the 7.2M-triangle star's finest level
     (D3Q27), float32 populations for all its blocks, checked by properties
     that hold at any size:
@@ -153,7 +227,7 @@ def test_star7m_bounce_back_properties(c2):
     from paper_2512_01251_amd import geo_ibb, make_level
     from paper_2512_01251_amd.pipeline import links_dense
     from synth.populations import lattice_weights
-    w = c2
+    w = configs.star7m()
     say("[fullsize] star7m bounce-back")
     emb, _, _ = gpu_embed(w, "f32")
     dn = links_dense(emb)
@@ -219,23 +293,16 @@ def test_degenerate_fullsize_exact(name, precision):
 
 @pytest.fixture(scope="module")
 def c4():
-    w = configs.spheres64()
-    say("[fullsize] spheres64 oracle forest ...")
-    return w, oracle.embed(w.mesh, w.n0, w.lf, w.lattice, w.d_spec, with_links=False)
+    return _forest_and_links(configs.spheres64())
 
 
 @pytest.mark.parametrize("precision", ["f32", "f64"])
-def test_spheres64_forest_exact_and_links_sampled(c4, precision):
-    w, ref = c4
+def test_spheres64_forest_and_link_set(c4, precision):
+    w, ref, lset = c4
     say(f"[fullsize] spheres64 {precision}")
-    emb, _, _ = gpu_embed(w, precision)
-    for g, r in zip(emb.levels, ref["levels"]):
-        assert np.array_equal(g.bcoord.cpu().numpy(), r["bcoord"])
-        assert np.array_equal(g.solid.cpu().numpy().view(np.uint64), r["solid"]), f"solid L{r['level']}"
-        if "refine" in r:
-            assert np.array_equal(g.bclass.cpu().numpy(), r["bclass"])
-            assert np.array_equal(g.refine.cpu().numpy(), r["refine"])
-            assert np.array_equal(g.child_map.cpu().numpy(), r["child_map"])
+    emb, _, _ = gpu_embed(w, precision, with_mask=True)
+    _check_forest(emb, ref)
+    _check_link_set(emb, lset)
     _check_invariants(w, emb)
-    e = _check_links_sample(w, emb, np.random.default_rng(5), 20000)
-    say(f"[fullsize] spheres64 {precision} ok: {emb.links.n} links, sampled max |dq| {e:.2e}")
+    e, nt = _check_links_sample(w, emb, np.random.default_rng(5), 20000)
+    say(f"[fullsize] spheres64 {precision} ok: {emb.links.n} links, sampled max |dq| {e:.2e}, {nt} tied")
