@@ -56,7 +56,8 @@ enum {
     GEO_OK = 0,
     GEO_ERR_ARG = -1,       /* host-side argument check failed; nothing enqueued */
     GEO_ERR_WORKSPACE = -2, /* workspace smaller than geo_workspace_size(...)   */
-    GEO_ERR_DEVICE = -3     /* a HIP call or kernel launch failed                */
+    GEO_ERR_DEVICE = -3,    /* a HIP call or kernel launch failed                */
+    GEO_ERR_TOO_LARGE = -4  /* request exceeds the fixed scratch of a no-alloc call */
 };
 
 enum { GEO_F32 = 0, GEO_F64 = 1 };                 /* vertex storage type      */
@@ -216,6 +217,26 @@ int geo_cutlinks(const geo_mesh* mesh, const geo_level* lv, const geo_bins* rows
                  int64_t cap, int64_t* d_nlinks, int32_t* link_cell, uint8_t* link_dir,
                  float* link_q, int32_t* link_tri, uint64_t* d_stats, void* ws, size_t ws_bytes,
                  geo_stream_t stream);
+
+/*
+ * geo_cutlinks without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, outputs, order and error behaviour
+ * as geo_cutlinks, minus ws / ws_bytes: the call's scratch is a fixed device
+ * array of GEO_NOALLOC_SCRATCH_BYTES compiled into the library (one per GPU
+ * it runs on, held until the process ends).  The call allocates and frees
+ * nothing.  It returns GEO_ERR_TOO_LARGE, before any device call and with
+ * nothing enqueued, when geo_workspace_size(GEO_CALL_CUTLINKS, nblocks, cap)
+ * exceeds GEO_NOALLOC_SCRATCH_BYTES.  Every call on one GPU shares that GPU's
+ * scratch, which keeps the previous call's contents (each call initialises
+ * what it reads): calls that overlap on one GPU (other streams, other host
+ * threads) race and give unspecified results; serialise them.
+ */
+#define GEO_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int geo_cutlinks_noalloc(const geo_mesh* mesh, const geo_level* lv, const geo_bins* rows,
+                         const geo_bins* links, int32_t lattice, int32_t precision, uint32_t* link_mask,
+                         int64_t cap, int64_t* d_nlinks, int32_t* link_cell, uint8_t* link_dir,
+                         float* link_q, int32_t* link_tri, uint64_t* d_stats, geo_stream_t stream);
 
 /*
  * Dense per-block layout of a cut-link table (Methodology, "Memory

@@ -15,7 +15,8 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgeo.so")
 
-GEO_OK, GEO_ERR_ARG, GEO_ERR_WORKSPACE, GEO_ERR_DEVICE = 0, -1, -2, -3
+GEO_OK, GEO_ERR_ARG, GEO_ERR_WORKSPACE, GEO_ERR_DEVICE, GEO_ERR_TOO_LARGE = 0, -1, -2, -3, -4
+GEO_NOALLOC_SCRATCH_BYTES = 64 << 20
 GEO_F32, GEO_F64 = 0, 1
 GEO_PREC_F64, GEO_PREC_F32_FALLBACK = 0, 1
 GEO_BINS_ROWS, GEO_BINS_LINKS = 0, 1
@@ -30,7 +31,7 @@ GEO_MAX_LEVELS = 12
 GEO_MAX_RES = 32767
 
 EXPORTS = ["geo_workspace_size", "geo_nprop", "geo_level0_blocks", "geo_build_bins", "geo_voxelize",
-           "geo_refine_flags", "geo_cutlinks", "geo_cutlinks_backward", "geo_links_dense", "geo_ibb", "geo_block_neighbours", "geo_solid_change", "geo2_level0_blocks", "geo2_build_bins",
+           "geo_refine_flags", "geo_cutlinks", "geo_cutlinks_noalloc", "geo_cutlinks_backward", "geo_links_dense", "geo_ibb", "geo_block_neighbours", "geo_solid_change", "geo2_level0_blocks", "geo2_build_bins",
            "geo2_voxelize", "geo2_refine_flags", "geo2_cutlinks", "geo_kernel_timer", "geo_kernel_timer_read", "geo_version"]
 
 
@@ -83,6 +84,7 @@ def lib():
         L.geo_voxelize.argtypes = [LP, BP, P, P]
         L.geo_refine_flags.argtypes = [LP, P, i32, P, P, P, P, P, P, sz, P]
         L.geo_cutlinks.argtypes = [MP, LP, BP, BP, i32, i32, P, i64, P, P, P, P, P, P, P, sz, P]
+        L.geo_cutlinks_noalloc.argtypes = [MP, LP, BP, BP, i32, i32, P, i64, P, P, P, P, P, P, P]
         L.geo_cutlinks_backward.argtypes = [MP, LP, i64, P, P, P, P, P, P]
         L.geo_links_dense.argtypes = [LP, i64, P, P, P, P, i32, i64, P, P, P, P, P, sz, P]
         L.geo_ibb.argtypes = [LP, P, P, P, i64, P, i32, i32, i32, P, P, P, P]
@@ -103,9 +105,14 @@ def lib():
     return _lib
 
 
+_STATUS = {GEO_ERR_ARG: "invalid argument", GEO_ERR_WORKSPACE: "workspace too small",
+           GEO_ERR_DEVICE: "HIP call or launch failed",
+           GEO_ERR_TOO_LARGE: f"request exceeds the {GEO_NOALLOC_SCRATCH_BYTES >> 20} MiB scratch of a no-alloc call"}
+
+
 def _check(rc: int, what: str):
     if rc != GEO_OK:
-        raise GeoError(f"{what} failed with status {rc}")
+        raise GeoError(f"{what} failed with status {rc} ({_STATUS.get(rc, 'unknown status')})")
 
 
 def _ptr(t):
@@ -228,6 +235,15 @@ def geo_cutlinks(mesh: geo_mesh, level: geo_level, rows: geo_bins, links: geo_bi
                             _ptr(link_dir), _ptr(link_q), _ptr(link_tri), _ptr(stats), _ptr(ws),
                             ws.numel() if ws is not None else 0, _stream(stream))
     _check(rc, "geo_cutlinks")
+
+
+def geo_cutlinks_noalloc(mesh: geo_mesh, level: geo_level, rows: geo_bins, links: geo_bins, lattice: int,
+                         precision: int, link_mask, cap: int, d_nlinks, link_cell, link_dir, link_q, link_tri,
+                         stats, stream=None):
+    rc = lib().geo_cutlinks_noalloc(C.byref(mesh), C.byref(level), C.byref(rows), C.byref(links), int(lattice),
+                                    int(precision), _ptr(link_mask), int(cap), _ptr(d_nlinks), _ptr(link_cell),
+                                    _ptr(link_dir), _ptr(link_q), _ptr(link_tri), _ptr(stats), _stream(stream))
+    _check(rc, "geo_cutlinks_noalloc")
 
 
 def geo_links_dense(level: geo_level, n_links: int, link_cell, link_dir, link_q, link_tri, lattice: int,

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = ["geo_scan.hip", "geo_bins.hip", "geo_voxelize.hip", "geo_refine.hip", "geo_cutlinks.hip",
-       "geo_backward.hip", "geo_dense.hip", "geo_ibb.hip", "geo_change.hip", "geo2d.hip", "geo_timer.hip", "geo_api.hip"]
+       "geo_backward.hip", "geo_dense.hip", "geo_ibb.hip", "geo_change.hip", "geo2d.hip", "geo_timer.hip", "geo_api.hip",
+       "geo_noalloc.hip"]
 LIB = os.path.join(HERE, "libgeo.so")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-munsafe-fp-atomics",
          # packed float32 instructions are disabled on purpose

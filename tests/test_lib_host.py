@@ -283,3 +283,27 @@ def test_2d_arguments_are_checked_on_the_host(geo):
     assert L.geo2_refine_flags(C.byref(lv), None, 0, None, None, None, None, None, None, 0,
                                None) == geo.GEO_ERR_ARG
     assert geo.geo_workspace_size(geo.GEO_CALL2_REFINE, 100, 0) > 8 * 4 * 100
+
+
+def test_noalloc_cutlinks_rejects_oversize_requests_before_any_device_call(geo):
+    """geo_cutlinks_noalloc checks the request against its fixed scratch
+    before touching a device: over the limit it returns GEO_ERR_TOO_LARGE,
+    and missing descriptors are GEO_ERR_ARG, both with nothing enqueued (this
+    runs without a GPU)."""
+    L = geo.lib()
+    lv = geo.geo_level()
+    for a in range(3):
+        lv.n0[a] = 32
+    lv.level = 0
+    lv.nblocks = 512
+    mesh = geo.geo_mesh(0, 0, geo.GEO_F32, None, None)
+    bins = geo.geo_bins()
+    over = 1 << 24
+    assert geo.geo_workspace_size(geo.GEO_CALL_CUTLINKS, 512, over) > geo.GEO_NOALLOC_SCRATCH_BYTES
+    rc = L.geo_cutlinks_noalloc(C.byref(mesh), C.byref(lv), C.byref(bins), C.byref(bins), 19,
+                                geo.GEO_PREC_F32_FALLBACK, None, over, None, None, None, None, None, None, None)
+    assert rc == geo.GEO_ERR_TOO_LARGE
+    rc = L.geo_cutlinks_noalloc(None, C.byref(lv), C.byref(bins), C.byref(bins), 19, geo.GEO_PREC_F32_FALLBACK,
+                                None, 16, None, None, None, None, None, None, None)
+    assert rc == geo.GEO_ERR_ARG
+    assert geo.geo_workspace_size(geo.GEO_CALL_CUTLINKS, 4096, 100000) <= geo.GEO_NOALLOC_SCRATCH_BYTES
