@@ -115,11 +115,13 @@ def q_kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def q_kernel_traffic():
-    """HBM bytes per launch of the q kernel from the committed counter profile,
-    or None when the kernel's sources changed since the counters were taken."""
+def q_kernel_counters():
+    """Counter figures of the q kernel (float32 form) from the committed
+    profile: HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
+    and the VALU issue fraction, or None for each when the kernel's sources
+    changed since the counters were taken."""
     if not os.path.exists(PMC_PROFILE):
-        return None, "no counter profile"
+        return {"traffic": None, "source": "no counter profile"}
     digest = q_kernel_source_hash()
     fields = {}
     for line in open(PMC_PROFILE):
@@ -127,55 +129,122 @@ def q_kernel_traffic():
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
     if fields.get("source_sha256") != digest:
-        return None, "kernel changed since the counters were taken"
-    return float(fields["traffic_bytes_per_launch"]), "FETCH_SIZE + WRITE_SIZE, copy-calibrated"
+        return {"traffic": None, "source": "kernel changed since the counters were taken"}
+    out = {"traffic": float(fields["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in fields else None,
+           "source": "FETCH_SIZE + WRITE_SIZE, copy-calibrated"}
+    for k in ("valu_issue_frac", "valu_lane_util", "valu_insts_per_launch", "fp32_flop_per_launch"):
+        if k in fields:
+            out[k] = float(fields[k])
+    return out
 
 
-def cpu_baseline(w, out, chunk_blocks=120000, min_seconds=10.0, max_chunks=16, with_links=False,
-                 n_links=20000):
-    """The oracle (as it stands) on a bounded random sample of the same
-    workload: chunks of every cell of chunk_blocks blocks drawn uniformly from
-    the blocks of all levels (exact point classification, the oracle's bucket
-    build included in every chunk), until min_seconds of CPU work."""
-    import oracle
-    rng = np.random.default_rng(0)
+def _sample_cells(rng, out, n_blocks):
+    """Cell centres of all 64 cells of n_blocks blocks drawn uniformly from the
+    blocks of all levels, with the GPU's solid flag of each."""
     counts = np.array([lv.bcoord.shape[0] for lv in out.levels])
-    bcs = [lv.bcoord.cpu().numpy() for lv in out.levels]
     t = np.arange(64)
     tc = np.stack([t & 3, (t >> 2) & 3, t >> 4], 1)
-    n_pts, secs, chunks = 0, 0.0, 0
-    while secs < min_seconds and chunks < max_chunks:
-        lvl = rng.choice(len(counts), chunk_blocks, p=counts / counts.sum())
-        pts = []
-        for L, bc in enumerate(bcs):
-            k = int((lvl == L).sum())
-            if k == 0:
-                continue
-            b = rng.integers(0, len(bc), k)
-            cells = (4 * bc[b])[:, None, :] + tc[None]
-            pts.append(((cells + 0.5) * 2.0 ** -L).reshape(-1, 3))
-        pts = np.concatenate(pts)
-        t0 = time.perf_counter()
-        oracle.solid_points(w.mesh, w.n0, pts)
-        secs += time.perf_counter() - t0
+    lvl = rng.choice(len(counts), n_blocks, p=counts / counts.sum())
+    pts, flags = [], []
+    for L, lv in enumerate(out.levels):
+        k = int((lvl == L).sum())
+        if k == 0:
+            continue
+        bc = lv.bcoord.cpu().numpy()
+        b = rng.integers(0, len(bc), k)
+        cells = (4 * bc[b])[:, None, :] + tc[None]
+        pts.append(((cells + 0.5) * 2.0 ** -L).reshape(-1, 3))
+        words = lv.solid.cpu().numpy().view(np.uint64)[b]
+        flags.append(((words[:, None] >> t.astype(np.uint64)[None, :]) & np.uint64(1)).astype(np.uint8).reshape(-1))
+    return np.concatenate(pts), np.concatenate(flags)
+
+
+def cpu_baseline(w, out, chunk_blocks=120000, min_seconds=10.0, max_chunks=16, n_links=100000,
+                 n_links_1t=10000, n_blocks=400):
+    """The oracle, as it stands, timed on the host's cores on bounded samples
+    of the same workload, and the GPU's error against it on those samples.
+
+    Cells: chunks of all 64 cells of chunk_blocks blocks drawn uniformly from
+    the blocks of every level (exact point classification), on all threads
+    until min_seconds of query time, then one chunk on one thread; the
+    oracle's bucket build, repeated by every call, is timed apart.  Links:
+    nearest hit (q and triangle) of n_links random links of the table on all
+    threads and n_links_1t on one.  Blocks: the oracle's whole link table of
+    n_blocks finest-level blocks (half with links, half drawn uniformly)
+    against the GPU's table for those blocks."""
+    import oracle
+    rng = np.random.default_rng(0)
+    threads = oracle.num_threads()
+    res = {"unit": "Mcells/s", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+           "nproc": os.cpu_count()}
+    # cells, all threads
+    n_pts, q_s, b_s, chunks, bad_cells = 0, 0.0, 0.0, 0, 0
+    while q_s < min_seconds and chunks < max_chunks:
+        pts, gpu_flags = _sample_cells(rng, out, chunk_blocks)
+        ref = oracle.solid_points(w.mesh, w.n0, pts)
+        tm = oracle.last_timing()
+        q_s += tm["query_s"]
+        b_s += tm["build_s"]
         n_pts += len(pts)
         chunks += 1
-    res = {"value": n_pts / secs / 1e6, "unit": "Mcells/s", "cores": oracle.num_threads(), "kind": "oracle",
-           "seconds": secs,
-           "sample": f"{chunks} chunks of all 64 cells of {chunk_blocks} blocks drawn uniformly from the blocks of "
-                     f"levels 0..{len(counts) - 1} ({n_pts} cells; exact point classification, bucket build "
-                     f"included in every chunk)"}
-    if with_links:
-        lv = out.levels[-1]
-        bc = bcs[-1]
-        li = rng.integers(0, out.links.n, min(n_links, out.links.n))
-        lc = out.links.cell.cpu().numpy()[li]
-        lcells = 4 * bc[lc // 64] + tc[lc % 64]
-        t0 = time.perf_counter()
-        oracle.q_points(w.mesh, w.n0, lv.level, lcells, out.links.dir.cpu().numpy()[li])
-        tl = time.perf_counter() - t0
-        res["mlinks_per_s"] = len(li) / tl / 1e6
-        res["links_sample"] = f"{len(li)} random links of the table (nearest hit, bucket build included)"
+        bad_cells += int(np.count_nonzero(ref != gpu_flags))
+    res["value"] = n_pts / q_s / 1e6
+    res["seconds"] = q_s
+    res["bucket_build_s_per_call"] = b_s / chunks
+    res["mcells_per_s_with_build"] = n_pts / (q_s + b_s) / 1e6
+    res["sample"] = (f"{chunks} chunks of all 64 cells of {chunk_blocks} blocks drawn uniformly from the blocks of "
+                     f"levels 0..{len(out.levels) - 1} ({n_pts} cells; exact point classification); value over "
+                     f"query time, the oracle's bucket build of every call timed apart")
+    # cells, one thread
+    oracle.set_threads(1)
+    pts1, _ = _sample_cells(rng, out, chunk_blocks // 8)
+    oracle.solid_points(w.mesh, w.n0, pts1)
+    tm = oracle.last_timing()
+    res["mcells_per_s_1thread"] = len(pts1) / tm["query_s"] / 1e6
+    oracle.set_threads(threads)
+    # links
+    lv = out.levels[-1]
+    bc = lv.bcoord.cpu().numpy()
+    t = np.arange(64)
+    tc = np.stack([t & 3, (t >> 2) & 3, t >> 4], 1)
+    lcell = out.links.cell.cpu().numpy()
+    ldir = out.links.dir.cpu().numpy()
+    lq = out.links.q.cpu().numpy().astype(np.float64)
+    ltri = out.links.tri.cpu().numpy()
+    li = rng.choice(out.links.n, min(n_links, out.links.n), replace=False)
+    cells = 4 * bc[lcell[li] // 64] + tc[lcell[li] % 64]
+    ref = oracle.q_points(w.mesh, w.n0, lv.level, cells, ldir[li])
+    tm = oracle.last_timing()
+    res["mlinks_per_s"] = len(li) / tm["query_s"] / 1e6
+    res["links_bucket_build_s"] = tm["build_s"]
+    dq = np.abs(lq[li] - ref["q"])
+    untied = ref["tied"] == 0
+    oracle.set_threads(1)
+    l1 = li[:n_links_1t]
+    oracle.q_points(w.mesh, w.n0, lv.level, cells[:len(l1)], ldir[l1])
+    res["mlinks_per_s_1thread"] = len(l1) / oracle.last_timing()["query_s"] / 1e6
+    oracle.set_threads(threads)
+    res["links_sample"] = (f"{len(li)} random links of the table on all threads, {len(l1)} on one (nearest hit over "
+                           f"the oracle's 3D buckets; build timed apart)")
+    # whole link tables of sampled blocks
+    gblk = lcell.astype(np.int64) // 64
+    with_links = np.unique(gblk)
+    sel = np.unique(np.concatenate([rng.choice(with_links, min(n_blocks // 2, len(with_links)), replace=False),
+                                    rng.choice(len(bc), min(n_blocks // 2, len(bc)), replace=False)]))
+    rb = oracle.links(w.mesh, w.n0, lv.level, bc[sel], w.lattice)
+    lo = np.searchsorted(gblk, sel, side="left")
+    hi = np.searchsorted(gblk, sel, side="right")
+    rows = np.concatenate([np.arange(a, b) for a, b in zip(lo, hi)])
+    gkey = set(zip((np.repeat(np.arange(len(sel)), hi - lo) * 64 + lcell[rows] % 64).tolist(), ldir[rows].tolist()))
+    okey = set(zip(rb["cell"].tolist(), rb["dir"].tolist()))
+    res["error_vs_oracle"] = {
+        "solid_mismatches": bad_cells, "solid_cells_checked": n_pts,
+        "link_set_mismatches": len(gkey ^ okey), "blocks_checked": int(len(sel)), "block_links": int(rb["n"]),
+        "q_max_abs_err": float(dq.max()), "q_p999_abs_err": float(np.quantile(dq, 0.999)),
+        "q_links_checked": int(len(li)),
+        "tri_mismatches_untied": int(np.count_nonzero(ltri[li][untied] != ref["tri"][untied])),
+        "tied_links": int(np.count_nonzero(~untied)),
+    }
     return res
 
 
@@ -348,7 +417,6 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="star7m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-cpu-links", action="store_true", help="skip the oracle's q on a link sample")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-bounce-back", action="store_true")
     ap.add_argument("--no-moving", action="store_true")
@@ -399,7 +467,7 @@ def main():
     flop = FLOP_PER_LINK_CAND * p_link + FLOP_PER_CELL_CAND * p_cell
     q_launch_ms = q_ms / q_n if q_n else float("nan")
     achieved = flop / (q_launch_ms * 1e-3) / 1e12
-    traffic, traffic_src = q_kernel_traffic()
+    qc = q_kernel_counters()
     line = {
         "metric": "Mcells/s voxelized + Mlinks/s q at 7.2M tris; FP32+fallback vs FP64 speedup",
         "value": cells / t32 / 1e6,
@@ -412,10 +480,10 @@ def main():
                    "base_grid": list(w.n0), "levels": w.lf + 1, "lattice": f"D3Q{w.lattice}",
                    "d_spec": w.d_spec},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
-                     "kernel": "k_cl_q<float>", "launch_ms": q_launch_ms, "launches": q_n,
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": qc.pop("traffic"),
+                     "kernel": "k_cl_q_f32", "launch_ms": q_launch_ms, "launches": q_n,
                      "flop_per_launch": flop, "link_cand_pairs": p_link, "cell_cand_pairs": p_cell,
-                     "traffic_source": traffic_src},
+                     "counters": qc},
         "ms_per_step_ci95": ci32 * 1e3 if ci32 else None,
         "cells": cells, "links": n_links, "link_bin_entries": int(out.links.bins_val.numel()),
         "blocks_per_level": [int(lv.bcoord.shape[0]) for lv in out.levels],
@@ -425,7 +493,8 @@ def main():
         "mlinks_per_s_with_bins": n_links / (lnk / 1e3) / 1e6 if lnk else None,
         "call_ms_f32": {k: round(v, 4) for k, v in calls32.items()},
         "kernel_ms_f32": kern32,
-        "stats_f32": dict(zip(["f32_to_f64", "exact", "links_exact", "contract", "staged", "pairs", "tasks"], stats)),
+        "stats_f32": dict(zip(["undecided", "exact", "links_exact", "contract", "staged", "pairs", "tasks", "t_f64"],
+                              stats)),
         **res64,
     }
     # the paper's dense per-block layout of the table (a solver-facing view,
@@ -457,7 +526,11 @@ def main():
     del dn
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(w, out, with_links=not args.no_cpu_links)
+        line["cpu_baseline"] = cpu_baseline(w, out)
+        st = line["stats_f32"]
+        line["cpu_baseline"]["error_vs_oracle"].update({
+            "undecided_pairs_per_link": st["undecided"] / max(n_links, 1),
+            "links_redone_exactly": st["links_exact"], "t_float64_per_link": st["t_f64"] / max(n_links, 1)})
     print(json.dumps(line), flush=True)
 
 

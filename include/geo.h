@@ -78,14 +78,19 @@ enum {
 
 /* device statistics counters (uint64 each) */
 enum {
-    GEO_STAT_F32_TO_F64 = 0, /* float32 sign tests re-evaluated in float64          */
+    GEO_STAT_F32_TO_F64 = 0, /* float32 sign tests left undecided by their filters:
+                                rows pass re-evaluated in float64; q kernel (both
+                                forms) pairs whose links the exact pass redoes   */
     GEO_STAT_EXACT = 1,      /* float64 sign tests resolved by exact arithmetic     */
     GEO_STAT_LINKS_EXACT = 2, /* links whose nearest hit was redone exactly          */
     GEO_STAT_CONTRACT = 3,   /* vertex coordinates outside the documented range     */
     GEO_STAT_STAGED = 4,     /* candidate triangles staged by the q kernel          */
     GEO_STAT_PAIRS = 5,      /* (link, candidate) pairs passing the box test        */
     GEO_STAT_TASKS = 6,      /* (64 links x 64 candidates) tasks of the q kernel     */
-    GEO_NSTATS = 7
+    GEO_STAT_T_F64 = 7,      /* float32-form hits whose parameter t was recomputed
+                                in float64 (its float32 error bound exceeded the
+                                share of the 1e-5 q tolerance)                    */
+    GEO_NSTATS = 8
 };
 
 #define GEO_MAX_LEVELS 12

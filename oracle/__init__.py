@@ -78,6 +78,8 @@ def lib():
         L.or_grad.argtypes = [P, P, i32, P, i32, i64, P, i64, P, P, P, P, i32, P]
         L.or_q_given.argtypes = [P, P, i32, P, i32, i64, P, P, P, P, P]
         L.or_num_threads.restype = i32
+        L.or_last_timing.argtypes = [P]
+        L.or_set_threads.argtypes = [i32]
         L.or2_solid_point.argtypes = [P, P, P, i32, P]
         L.or2_classify_blocks.argtypes = [P, P, i32, P, i32, i64, P, i32, P]
         L.or2_refine.argtypes = [P, i32, i64, P, P, i32, P, P, P, P]
@@ -111,6 +113,19 @@ def orient3d(a, b, c, d, exact_only: bool = False) -> int:
 
 def num_threads() -> int:
     return lib().or_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """OpenMP thread count of later oracle calls."""
+    lib().or_set_threads(int(n))
+
+
+def last_timing() -> dict:
+    """Wall seconds of the last solid_points / q_points call: its bucket
+    build, and the queries after it."""
+    out = np.zeros(2, np.float64)
+    lib().or_last_timing(_p(out))
+    return {"build_s": float(out[0]), "query_s": float(out[1])}
 
 
 # ----------------------------------------------------------------------------

@@ -211,6 +211,23 @@ int or_solid_point(const double* V, const int32_t* T, const int32_t* cand, int n
 }
 
 /* brute force over all triangles (no filter) */
+/* wall time of the last bucket build and of the queries that followed it,
+ * per entry point call (for the benchmark's CPU baseline) */
+static double g_t_build = 0.0, g_t_query = 0.0;
+
+void or_last_timing(double* out) {
+    out[0] = g_t_build;
+    out[1] = g_t_query;
+}
+
+void or_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 void or_solid_points_brute(const double* V, const int32_t* T, int nt, int64_t npts,
                            const double* pts, uint8_t* out) {
     int32_t* all = (int32_t*)malloc(sizeof(int32_t) * (nt > 0 ? nt : 1));
@@ -223,8 +240,10 @@ void or_solid_points_brute(const double* V, const int32_t* T, int nt, int64_t np
 /* filtered by triangles whose yz box contains the point */
 void or_solid_points(const double* V, const int32_t* T, int nt, const int32_t* n0, int64_t npts,
                      const double* pts, uint8_t* out) {
+    double w0 = omp_get_wtime();
     buckets B;
     buckets_build(&B, 2, V, T, nt, n0);
+    double w1 = omp_get_wtime();
 #pragma omp parallel
     {
         int32_t* buf = NULL;
@@ -237,6 +256,8 @@ void or_solid_points(const double* V, const int32_t* T, int nt, const int32_t* n
         }
         free(buf);
     }
+    g_t_build = w1 - w0;
+    g_t_query = omp_get_wtime() - w1;
     buckets_free(&B);
 }
 
@@ -544,8 +565,10 @@ int64_t or_links(const double* V, const int32_t* T, int nt, const int32_t* n0, i
 void or_q_points(const double* V, const int32_t* T, int nt, const int32_t* n0, int L, int64_t n,
                  const int32_t* cell, const uint8_t* dir, double* q_out, int32_t* tri_out,
                  uint8_t* tied_out) {
+    double w0 = omp_get_wtime();
     buckets B;
     buckets_build(&B, 3, V, T, nt, n0);
+    double w1 = omp_get_wtime();
     double h = ldexp(1.0, -L);
 #pragma omp parallel
     {
@@ -569,6 +592,8 @@ void or_q_points(const double* V, const int32_t* T, int nt, const int32_t* n0, i
         }
         free(buf);
     }
+    g_t_build = w1 - w0;
+    g_t_query = omp_get_wtime() - w1;
     buckets_free(&B);
 }
 

@@ -23,8 +23,8 @@ GEO_BINS_ROWS, GEO_BINS_LINKS = 0, 1
 GEO_CALL_BINS_ROWS, GEO_CALL_BINS_LINKS, GEO_CALL_REFINE, GEO_CALL_CUTLINKS, GEO_CALL_LINKS_DENSE = 0, 1, 2, 3, 4
 GEO_CALL2_BINS, GEO_CALL2_REFINE, GEO_CALL2_CUTLINKS = 5, 6, 7
 GEO_STAT_F32_TO_F64, GEO_STAT_EXACT, GEO_STAT_LINKS_EXACT, GEO_STAT_CONTRACT, GEO_STAT_STAGED, GEO_STAT_PAIRS = 0, 1, 2, 3, 4, 5
-GEO_STAT_TASKS = 6
-GEO_NSTATS = 7
+GEO_STAT_TASKS, GEO_STAT_T_F64 = 6, 7
+GEO_NSTATS = 8
 GEO_KT_ROWS, GEO_KT_VOXELIZE, GEO_KT_LINKS_BINS, GEO_KT_CUTLINKS_Q, GEO_KT_IBB, GEO_KT_COUNT = 0, 1, 2, 3, 4, 5
 GEO_KT_MAX_LAUNCHES = 4096
 GEO_MAX_LEVELS = 12
