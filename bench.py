@@ -456,8 +456,18 @@ def main():
         t64, ci64, _ = run_steps(emb, V, T, w, "f64", args.steps)
         print(f"[bench] f64 {t64*1e3:.2f} ms/step", file=sys.stderr, flush=True)
         calls64, kern64, _ = call_times(emb, V, T, w, "f64")
+        lb32, lb64 = calls32.get("linkbins", 0.0), calls64.get("linkbins", 0.0)
+        q32 = kern32["k_cl_q"]["ms_per_launch"]
+        q64 = kern64["k_cl_q"]["ms_per_launch"]
         res64 = {"ms_per_step_f64": t64 * 1e3, "ms_per_step_f64_ci95": ci64 * 1e3 if ci64 else None,
                  "speedup_step_f32_vs_f64": t64 / t32,
+                 # the LINKS-bin pass runs one conservative test in both forms
+                 # (float64 normal, float32 edge axes with margins): the step
+                 # speed-up is also given without it
+                 "speedup_step_without_link_bins": (t64 * 1e3 - lb64) / (t32 * 1e3 - lb32),
+                 "speedup_cutlinks_call": calls64["cutlinks"] / calls32["cutlinks"] if calls32.get("cutlinks") else None,
+                 "speedup_q_kernel": q64 / q32 if q32 and q64 else None,
+                 "link_bins_shared_by_forms": True,
                  "call_ms_f64": {k: round(v, 4) for k, v in calls64.items()}, "kernel_ms_f64": kern64}
     vox_only = sum(v for k, v in calls32.items() if k.startswith("voxelize"))
     vox = sum(v for k, v in calls32.items() if k.startswith("rows") or k.startswith("voxelize"))
