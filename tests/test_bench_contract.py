@@ -42,8 +42,8 @@ def test_traffic_is_taken_only_for_the_profiled_kernel(tmp_path, monkeypatch):
     prof = tmp_path / "profile.txt"
     prof.write_text(f"source_sha256: {bench.q_kernel_source_hash()}\ntraffic_bytes_per_launch: 123.0\n")
     monkeypatch.setattr(bench, "PMC_PROFILE", str(prof))
-    value, note = bench.q_kernel_traffic()
-    assert value == 123.0, note
+    c = bench.q_kernel_counters()
+    assert c["traffic"] == 123.0, c["source"]
 
     marker = b"// host-side launchers"
     cases = {
@@ -57,5 +57,5 @@ def test_traffic_is_taken_only_for_the_profiled_kernel(tmp_path, monkeypatch):
         d = tmp_path / name.replace(" ", "_")
         d.mkdir()
         monkeypatch.setattr(bench, "Q_KERNEL_SOURCES", _copy_sources(sources, d, edit))
-        value, note = bench.q_kernel_traffic()
-        assert (value is not None) == kept, (name, note)
+        c = bench.q_kernel_counters()
+        assert (c["traffic"] is not None) == kept, (name, c["source"])
