@@ -159,6 +159,20 @@ def _sample_cells(rng, out, n_blocks):
     return np.concatenate(pts), np.concatenate(flags)
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo; the platform string where
+    that is not available)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(w, out, chunk_blocks=120000, min_seconds=10.0, max_chunks=16, n_links=100000,
                  n_links_1t=10000, n_blocks=400):
     """The oracle, as it stands, timed on the host's cores on bounded samples
@@ -179,7 +193,7 @@ def cpu_baseline(w, out, chunk_blocks=120000, min_seconds=10.0, max_chunks=16, n
            "nproc": os.cpu_count()}
     # cells, all threads
     n_pts, q_s, b_s, chunks, bad_cells = 0, 0.0, 0.0, 0, 0
-    while q_s < min_seconds and chunks < max_chunks:
+    while chunks == 0 or (q_s < min_seconds and chunks < max_chunks):
         pts, gpu_flags = _sample_cells(rng, out, chunk_blocks)
         ref = oracle.solid_points(w.mesh, w.n0, pts)
         tm = oracle.last_timing()

@@ -59,3 +59,32 @@ def test_traffic_is_taken_only_for_the_profiled_kernel(tmp_path, monkeypatch):
         monkeypatch.setattr(bench, "Q_KERNEL_SOURCES", _copy_sources(sources, d, edit))
         c = bench.q_kernel_counters()
         assert (c["traffic"] is not None) == kept, (name, c["source"])
+
+
+def test_cpu_baseline_leg_runs_on_the_host():
+    """bench.py's cpu_baseline leg end to end on a small workload, fed the
+    oracle's own embedding in place of the GPU's (CPU tensors): every field
+    is produced, and the error against the oracle is zero on every output."""
+    from types import SimpleNamespace as NS
+
+    import numpy as np
+    import torch
+
+    import bench
+    import oracle
+    from synth import configs
+    w = configs.star_small()
+    ref = oracle.embed(w.mesh, w.n0, w.lf, w.lattice, w.d_spec)
+    levels = [NS(level=r["level"], bcoord=torch.from_numpy(r["bcoord"]),
+                 solid=torch.from_numpy(r["solid"].view(np.int64))) for r in ref["levels"]]
+    rl = ref["links"]
+    links = NS(n=rl["n"], cell=torch.from_numpy(rl["cell"]), dir=torch.from_numpy(rl["dir"]),
+               q=torch.from_numpy(rl["q"].astype(np.float32)), tri=torch.from_numpy(rl["tri"]))
+    res = bench.cpu_baseline(w, NS(levels=levels, links=links), chunk_blocks=40, min_seconds=0.0, max_chunks=1,
+                             n_links=200, n_links_1t=50, n_blocks=20)
+    assert res["kind"] == "oracle" and res["cores"] >= 1 and res["cpu_model"]
+    for k in ("value", "mcells_per_s_1thread", "mlinks_per_s", "mlinks_per_s_1thread"):
+        assert res[k] > 0, k
+    e = res["error_vs_oracle"]
+    assert e["solid_mismatches"] == 0 and e["link_set_mismatches"] == 0
+    assert e["q_max_abs_err"] <= 1e-6 and e["tri_mismatches_untied"] == 0
