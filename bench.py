@@ -66,7 +66,7 @@ def call_times(emb, V, T, w, precision, reps=3):
     """Per-call device times (ms) from events around each C call, and per-kernel
     device times (ms per launch) from the library's kernel timer, averaged."""
     import paper_2512_01251_amd as geo
-    kernels = {"k_rows_pass1": geo.GEO_KT_ROWS, "k_voxelize": geo.GEO_KT_VOXELIZE,
+    kernels = {"k_rows": geo.GEO_KT_ROWS, "k_voxelize": geo.GEO_KT_VOXELIZE,
                "k_links_pass1": geo.GEO_KT_LINKS_BINS, "k_cl_q": geo.GEO_KT_CUTLINKS_Q}
     for k in kernels.values():
         geo.geo_kernel_timer(k, True)

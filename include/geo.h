@@ -73,7 +73,9 @@ enum {
     GEO_CALL_LINKS_DENSE = 4, /* nkeys = blocks of the level, cap ignored */
     GEO_CALL2_BINS = 5,       /* 2D bins: nkeys = row lines (ROWS) or blocks (LINKS) */
     GEO_CALL2_REFINE = 6,     /* 2D refinement: nkeys = blocks                       */
-    GEO_CALL2_CUTLINKS = 7    /* 2D cut links: nkeys = blocks                        */
+    GEO_CALL2_CUTLINKS = 7,   /* 2D cut links: nkeys = blocks                        */
+    GEO_CALL_BINS_ROWS_LEVELS = 8 /* ROWS bins of several levels: nkeys = the levels'
+                                     lines together, cap = their capacities together */
 };
 
 /* device statistics counters (uint64 each) */
@@ -168,6 +170,33 @@ int geo_level0_blocks(const int32_t n0[3], int32_t* bcoord, geo_stream_t stream)
 int geo_build_bins(const geo_mesh* mesh, const geo_level* lv, int32_t kind, int32_t precision,
                    geo_bins* out, uint64_t* d_stats, void* ws, size_t ws_bytes,
                    geo_stream_t stream);
+
+/*
+ * ROWS bins of levels lmin .. lmin+nlev-1 in one pass over the triangles
+ * (Methodology, "Spatial Binning"; the bins are built for every level of the
+ * forest, and they do not depend on the level's blocks).  out[l] receives the
+ * ROWS bins of level lmin+l with the same entries per line as
+ * geo_build_bins(mesh, level lmin+l, GEO_BINS_ROWS, precision, ...) gives
+ * (the order within a line is unspecified in both); each triangle is read
+ * once and visits its lines of every level in turn.
+ *
+ * n0: base cells per axis (host int32[3], multiples of 4); 0 <= lmin,
+ * 1 <= nlev, lmin + nlev <= GEO_MAX_LEVELS, n0[a] 2^(lmin+nlev-1) <=
+ * GEO_MAX_RES.  out: host array of nlev bins descriptors (kind GEO_BINS_ROWS,
+ * nkeys = n0y 2^L n0z 2^L of their level, distinct d_count words); the sum of
+ * their nkeys must stay below 2^31 - 1.  Every *d_count is written with the
+ * number of entries its level needs.  The entries of every level are complete
+ * only when no level's count exceeds its cap: the levels share one staging
+ * array, so an overflow of one level leaves every level's val unspecified
+ * (the counts stay exact); the caller then rebuilds with larger caps.
+ * d_stats: as for geo_build_bins (summed over the levels).  Workspace:
+ * geo_workspace_size(GEO_CALL_BINS_ROWS_LEVELS, sum of the levels' nkeys,
+ * sum of their caps).  Returns GEO_ERR_ARG or GEO_ERR_WORKSPACE with nothing
+ * enqueued when an argument is out of range.
+ */
+int geo_build_row_bins_levels(const geo_mesh* mesh, const int32_t n0[3], int32_t lmin, int32_t nlev,
+                              int32_t precision, const geo_bins* out, uint64_t* d_stats, void* ws,
+                              size_t ws_bytes, geo_stream_t stream);
 
 /*
  * Solid voxelization of level L (Methodology, "Partial Surface Voxelization"

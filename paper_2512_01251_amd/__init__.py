@@ -22,6 +22,7 @@ GEO_PREC_F64, GEO_PREC_F32_FALLBACK = 0, 1
 GEO_BINS_ROWS, GEO_BINS_LINKS = 0, 1
 GEO_CALL_BINS_ROWS, GEO_CALL_BINS_LINKS, GEO_CALL_REFINE, GEO_CALL_CUTLINKS, GEO_CALL_LINKS_DENSE = 0, 1, 2, 3, 4
 GEO_CALL2_BINS, GEO_CALL2_REFINE, GEO_CALL2_CUTLINKS = 5, 6, 7
+GEO_CALL_BINS_ROWS_LEVELS = 8
 GEO_STAT_F32_TO_F64, GEO_STAT_EXACT, GEO_STAT_LINKS_EXACT, GEO_STAT_CONTRACT, GEO_STAT_STAGED, GEO_STAT_PAIRS = 0, 1, 2, 3, 4, 5
 GEO_STAT_TASKS, GEO_STAT_T_F64 = 6, 7
 GEO_NSTATS = 8
@@ -30,7 +31,7 @@ GEO_KT_MAX_LAUNCHES = 4096
 GEO_MAX_LEVELS = 12
 GEO_MAX_RES = 32767
 
-EXPORTS = ["geo_workspace_size", "geo_nprop", "geo_level0_blocks", "geo_build_bins", "geo_voxelize",
+EXPORTS = ["geo_workspace_size", "geo_nprop", "geo_level0_blocks", "geo_build_bins", "geo_build_row_bins_levels", "geo_voxelize",
            "geo_refine_flags", "geo_cutlinks", "geo_cutlinks_noalloc", "geo_cutlinks_backward", "geo_links_dense", "geo_ibb", "geo_block_neighbours", "geo_solid_change", "geo2_level0_blocks", "geo2_build_bins",
            "geo2_voxelize", "geo2_refine_flags", "geo2_cutlinks", "geo_kernel_timer", "geo_kernel_timer_read", "geo_version"]
 
@@ -81,6 +82,7 @@ def lib():
         L.geo_nprop.restype = i32
         L.geo_level0_blocks.argtypes = [P, P, P]
         L.geo_build_bins.argtypes = [MP, LP, i32, i32, BP, P, P, sz, P]
+        L.geo_build_row_bins_levels.argtypes = [MP, C.POINTER(C.c_int32), i32, i32, i32, BP, P, P, sz, P]
         L.geo_voxelize.argtypes = [LP, BP, P, P]
         L.geo_refine_flags.argtypes = [LP, P, i32, P, P, P, P, P, P, sz, P]
         L.geo_cutlinks.argtypes = [MP, LP, BP, BP, i32, i32, P, i64, P, P, P, P, P, P, P, sz, P]
@@ -212,6 +214,17 @@ def geo_build_bins(mesh: geo_mesh, level: geo_level, kind: int, precision: int, 
                               _ptr(stats), _ptr(ws), ws.numel() if ws is not None else 0,
                               _stream(stream))
     _check(rc, "geo_build_bins")
+
+
+def geo_build_row_bins_levels(mesh: geo_mesh, n0, lmin: int, precision: int, bins, stats, ws, stream=None):
+    """ROWS bins of levels lmin .. lmin+len(bins)-1 in one call; bins: a
+    sequence of geo_bins, one per level."""
+    n = len(bins)
+    arr = (geo_bins * max(n, 1))(*bins)
+    n0c = (C.c_int32 * 3)(*[int(x) for x in n0])
+    rc = lib().geo_build_row_bins_levels(C.byref(mesh), n0c, lmin, n, precision, arr, _ptr(stats), _ptr(ws),
+                                         ws.numel() if ws is not None else 0, _stream(stream))
+    _check(rc, "geo_build_row_bins_levels")
 
 
 def geo_voxelize(level: geo_level, rows: geo_bins, solid, stream=None):

@@ -17,6 +17,8 @@ size_t bins_ws_bytes(int64_t nkeys, int64_t cap) {
            al(geo_scan_partials_bytes(nkeys));
 }
 
+size_t rows_levels_ws_bytes(int64_t nkeys, int64_t cap) { return bins_ws_bytes(nkeys, cap) + al(sizeof(int64_t)); }
+
 bool check_level(const geo_level* lv) {
     if (!lv) return false;
     if (lv->level < 0 || lv->level >= GEO_MAX_LEVELS || lv->nblocks < 0) return false;
@@ -63,6 +65,7 @@ size_t geo_workspace_size(int32_t call, int64_t nkeys, int64_t cap) {
     switch (call) {
         case GEO_CALL_BINS_ROWS:
         case GEO_CALL_BINS_LINKS: return bins_ws_bytes(nkeys, cap);
+        case GEO_CALL_BINS_ROWS_LEVELS: return rows_levels_ws_bytes(nkeys, cap);
         case GEO_CALL_REFINE: return geo_refine_ws_bytes(nkeys);
         case GEO_CALL_CUTLINKS: return geo_cutlinks_ws_bytes(nkeys, cap);
         case GEO_CALL_LINKS_DENSE: return geo_dense_ws_bytes(nkeys);
@@ -127,6 +130,62 @@ int geo_build_bins(const geo_mesh* mesh, const geo_level* lv, int32_t kind, int3
     if (rc != GEO_OK) return rc;
     if ((rc = geo_scan_exclusive(cnt, out->off, nkeys, partials, s)) != GEO_OK) return rc;
     return launch_bins_scatter(pairs, rank, out->cap, out->d_count, out->off, out->val, s);
+}
+
+int geo_build_row_bins_levels(const geo_mesh* mesh, const int32_t n0[3], int32_t lmin, int32_t nlev,
+                              int32_t precision, const geo_bins* out, uint64_t* d_stats, void* ws, size_t ws_bytes,
+                              geo_stream_t stream) {
+    if (!check_mesh(mesh) || !n0 || !out) return GEO_ERR_ARG;
+    if (lmin < 0 || nlev < 1 || lmin + nlev > GEO_MAX_LEVELS) return GEO_ERR_ARG;
+    if (precision != GEO_PREC_F64 && precision != GEO_PREC_F32_FALLBACK) return GEO_ERR_ARG;
+    geo_level lv{};
+    for (int a = 0; a < 3; a++) lv.n0[a] = n0[a];
+    lv.level = lmin + nlev - 1;  // the finest level bounds the resolution
+    if (!check_level(&lv)) return GEO_ERR_ARG;
+    RowLevels rl{};
+    rl.nlev = nlev;
+    rl.lmin = lmin;
+    int64_t nkeys = 0, cap = 0;
+    for (int l = 0; l < nlev; l++) {
+        lv.level = lmin + l;
+        const int64_t nk = row_keys(&lv);
+        if (!check_bins(&out[l], GEO_BINS_ROWS, nk)) return GEO_ERR_ARG;
+        for (int q = 0; q < l; q++)
+            if (out[q].d_count == out[l].d_count) return GEO_ERR_ARG;  // each level counts on its own
+        rl.base[l] = (int)nkeys;
+        nkeys += nk;
+        if (nkeys + 1 > INT32_MAX) return GEO_ERR_ARG;
+        rl.count[l] = reinterpret_cast<unsigned long long*>(out[l].d_count);
+        rl.off[l] = out[l].off;
+        rl.val[l] = out[l].val;
+        rl.cap[l] = out[l].cap;
+        cap += out[l].cap;
+    }
+    for (int l = nlev; l <= GEO_MAX_LEVELS; l++) rl.base[l] = (int)nkeys;
+    if (ws_bytes < rows_levels_ws_bytes(nkeys, cap) || (!ws && ws_bytes)) return GEO_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    char* p = static_cast<char*>(ws);
+    int2* pairs = reinterpret_cast<int2*>(p);
+    p += al(sizeof(int2) * (size_t)cap);
+    int32_t* rank = reinterpret_cast<int32_t*>(p);
+    p += al(sizeof(int32_t) * (size_t)cap);
+    int32_t* cnt = reinterpret_cast<int32_t*>(p);
+    p += al(sizeof(int32_t) * ((size_t)nkeys + 1));
+    int32_t* partials = reinterpret_cast<int32_t*>(p);
+    p += al(geo_scan_partials_bytes(nkeys));
+    int64_t* d_pairs = reinterpret_cast<int64_t*>(p);
+    lv.level = lmin;
+    const DevMesh m = dev_mesh(mesh);
+    const DevLevel d = dev_level(&lv);
+    int rc;
+    if ((rc = launch_rows_levels_zero(rl, d_pairs, s)) != GEO_OK) return rc;
+    if ((rc = geo_fill_i32(cnt, 0, nkeys, s)) != GEO_OK) return rc;
+    if ((rc = launch_check_mesh(m, d, d_stats, s)) != GEO_OK) return rc;
+    if ((rc = launch_rows_levels(m, d, precision, rl, cnt, pairs, rank, cap, d_pairs, d_stats, s)) != GEO_OK)
+        return rc;
+    for (int l = 0; l < nlev; l++)
+        if ((rc = geo_scan_exclusive(cnt + rl.base[l], out[l].off, out[l].nkeys, partials, s)) != GEO_OK) return rc;
+    return launch_rows_levels_scatter(pairs, rank, cap, d_pairs, rl, s);
 }
 
 int geo_voxelize(const geo_level* lv, const geo_bins* rows, uint64_t* solid, geo_stream_t stream) {

@@ -114,9 +114,10 @@ struct Appender {
         __syncthreads();
         n = 0;
     }
-    __device__ __forceinline__ void add(bool has, int key, int32_t val) {
+    // returns the number of pairs added (identical in every lane)
+    __device__ __forceinline__ int add(bool has, int key, int32_t val) {
         const unsigned long long mask = __ballot(has);
-        if (mask == 0ull) return;
+        if (mask == 0ull) return 0;
         const int k = __popcll(mask);
         if (n + k > APP_BUF) flush();
         if (has) {
@@ -124,6 +125,7 @@ struct Appender {
             buf[n + __popcll(mask & ((1ull << lane) - 1ull))] = make_int2(key, val);
         }
         n += k;
+        return k;
     }
 };
 
@@ -242,15 +244,27 @@ __device__ __forceinline__ int sos_tie(const DevMesh& m, const RowTri<R>& T, dou
     return 0;
 }
 
-// Set up the local frame.  Returns false for triangles with no line.
-template <typename R>
-__device__ bool row_setup(const DevMesh& m, int t, int L, int ny, int nz, RowTri<R>& T, int& jlo,
-                          int& jhi, int& klo, int& khi) {
-    const double s = ldexp(1.0, L);
-    int id[3] = {m.tris[3 * (int64_t)t], m.tris[3 * (int64_t)t + 1], m.tris[3 * (int64_t)t + 2]};
-    double X[3][3];
+// vertex ids and coordinates of one triangle, loaded once for every level
+struct TriLoad {
+    int id[3];
+    double x[3][3];
+};
+
+__device__ __forceinline__ void tri_load(const DevMesh& m, int64_t t, TriLoad& tl) {
+    for (int i = 0; i < 3; i++) tl.id[i] = m.tris[3 * t + i];
     for (int i = 0; i < 3; i++)
-        for (int a = 0; a < 3; a++) X[i][a] = scaled64(m, id[i], a, s);
+        for (int a = 0; a < 3; a++) tl.x[i][a] = load_coord(m, tl.id[i], a);
+}
+
+// Set up the local frame of level L.  Returns false for triangles with no line.
+template <typename R>
+__device__ bool row_setup(const TriLoad& tl, int L, int ny, int nz, RowTri<R>& T, int& jlo, int& jhi,
+                          int& klo, int& khi) {
+    const double s = ldexp(1.0, L);
+    const int(&id)[3] = tl.id;
+    double X[3][3];  // the same float64 operations as scaled64
+    for (int i = 0; i < 3; i++)
+        for (int a = 0; a < 3; a++) X[i][a] = tl.x[i][a] * s - 0.5;
     const double ymin = fmin(X[0][1], fmin(X[1][1], X[2][1])), ymax = fmax(X[0][1], fmax(X[1][1], X[2][1]));
     const double zmin = fmin(X[0][2], fmin(X[1][2], X[2][2])), zmax = fmax(X[0][2], fmax(X[1][2], X[2][2]));
     jlo = (int)fmax(ceil(ymin), 0.0);
@@ -398,55 +412,149 @@ __device__ void row_events(const DevMesh& m, const RowTri<R>& T, double s, int m
     }
 }
 
+// The row-line events of one level for the wave's triangles (live lanes hold
+// one loaded triangle each), appended under keys key_base + j + ny k.  Called
+// by the whole wave; returns the number of pairs appended.
+template <typename R>
+__device__ __forceinline__ int rows_level(const DevMesh& m, bool live, const TriLoad& tl, int L, int key_base,
+                                          Appender<false>& app, Stats& st, const int n0[3]) {
+    const int nx = n0[0] << L, ny = n0[1] << L, nz = n0[2] << L;
+    const double s = ldexp(1.0, L);
+    RowTri<R> T;
+    int jlo = 0, jhi = -1, klo = 0, khi = -1;
+    int mode = 0, drop = 0, areaSign = 0;
+    if (live && row_setup<R>(tl, L, ny, nz, T, jlo, jhi, klo, khi)) {
+        const int ayz = chain_area<R>(m, T, s, 1, 2, st);
+        if (ayz < 0) swap_bc<R>(T);
+        if (ayz != 0) {
+            mode = 1;
+        } else {
+            // edge-on or degenerate: find a plane (x,y) or (x,z) with non-zero area
+            const int axy = chain_area<R>(m, T, s, 0, 1, st);
+            if (axy != 0) { mode = 2; drop = 1; areaSign = axy; }
+            else {
+                const int axz = chain_area<R>(m, T, s, 0, 2, st);
+                if (axz != 0) { mode = 2; drop = 2; areaSign = axz; }
+            }
+        }
+    }
+    const int nj = mode ? jhi - jlo + 1 : 0;
+    const int nlines = mode ? nj * (khi - klo + 1) : 0;
+    int added = 0;
+    for (int it = 0; __any(it < nlines); it++) {
+        bool h0 = false, h1 = false;
+        int32_t e0 = 0, e1 = 0;
+        int key = 0;
+        if (it < nlines) {
+            const int j = jlo + it % nj, k = klo + it / nj;
+            key = key_base + j + ny * k;
+            row_events<R>(m, T, s, mode, drop, areaSign, j, k, nx, st, h0, e0, h1, e1);
+        }
+        added += app.add(h0, key, e0);
+        added += app.add(h1, key, e1);
+    }
+    return added;
+}
+
 template <typename R>
 __global__ void __launch_bounds__(64) k_rows_pass1(DevMesh m, DevLevel d, int32_t* cnt, int2* pairs, int32_t* rank,
                                                    int64_t cap, int64_t* d_count, uint64_t* stats) {
     __shared__ int2 sbuf[APP_BUF];
     Appender<false> app{sbuf, 0, pairs, rank, cap, d_count, cnt};
-    const int L = d.level;
-    const int nx = d.n0[0] << L, ny = d.n0[1] << L, nz = d.n0[2] << L;
-    const double s = ldexp(1.0, L);
     Stats st;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m.nt; base += stride) {
         const int64_t t = base + threadIdx.x;
-        RowTri<R> T;
-        int jlo = 0, jhi = -1, klo = 0, khi = -1;
-        int mode = 0, drop = 0, areaSign = 0;
-        if (t < m.nt && row_setup<R>(m, (int)t, L, ny, nz, T, jlo, jhi, klo, khi)) {
-            const int ayz = chain_area<R>(m, T, s, 1, 2, st);
-            if (ayz < 0) swap_bc<R>(T);
-            if (ayz != 0) {
-                mode = 1;
-            } else {
-                // edge-on or degenerate: find a plane (x,y) or (x,z) with non-zero area
-                const int axy = chain_area<R>(m, T, s, 0, 1, st);
-                if (axy != 0) { mode = 2; drop = 1; areaSign = axy; }
-                else {
-                    const int axz = chain_area<R>(m, T, s, 0, 2, st);
-                    if (axz != 0) { mode = 2; drop = 2; areaSign = axz; }
-                }
-            }
-        }
-        const int nj = mode ? jhi - jlo + 1 : 0;
-        const int nlines = mode ? nj * (khi - klo + 1) : 0;
-        for (int it = 0; __any(it < nlines); it++) {
-            bool h0 = false, h1 = false;
-            int32_t e0 = 0, e1 = 0;
-            int key = 0;
-            if (it < nlines) {
-                const int j = jlo + it % nj, k = klo + it / nj;
-                key = j + ny * k;
-                row_events<R>(m, T, s, mode, drop, areaSign, j, k, nx, st, h0, e0, h1, e1);
-            }
-            app.add(h0, key, e0);
-            app.add(h1, key, e1);
-        }
+        TriLoad tl;
+        const bool live = t < m.nt;
+        if (live) tri_load(m, t, tl);
+        rows_level<R>(m, live, tl, d.level, 0, app, st, d.n0);
     }
     app.flush();
     if (stats) {
         if constexpr (std::is_same<R, float>::value) wave_count(&stats[GEO_STAT_F32_TO_F64], st.fb);
         wave_count(&stats[GEO_STAT_EXACT], st.ex);
+    }
+}
+
+// ROWS bins of levels lmin .. lmin+nlev-1 in one pass: each triangle is
+// loaded once and visits its lines of every level in turn; the keys of level
+// lmin+l start at rl.base[l].  Pairs share one array and one reservation
+// counter (*d_pairs); the pairs needed by each level are counted per wave in
+// LDS and added to the level's own counter once at the end.
+template <typename R>
+__device__ __forceinline__ void rows_levels_body(const DevMesh& m, const DevLevel& d, const RowLevels& rl, int32_t* cnt,
+                                                 int2* pairs, int32_t* rank, int64_t cap, int64_t* d_pairs,
+                                                 uint64_t* stats) {
+    __shared__ int2 sbuf[APP_BUF];
+    __shared__ unsigned long long slc[GEO_MAX_LEVELS];
+    const int lane = threadIdx.x;
+    if (lane < GEO_MAX_LEVELS) slc[lane] = 0;
+    __syncthreads();
+    Appender<false> app{sbuf, 0, pairs, rank, cap, d_pairs, cnt};
+    Stats st;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m.nt; base += stride) {
+        const int64_t t = base + lane;
+        TriLoad tl;
+        const bool live = t < m.nt;
+        if (live) tri_load(m, t, tl);
+        for (int l = 0; l < rl.nlev; l++) {
+            const int added = rows_level<R>(m, live, tl, rl.lmin + l, rl.base[l], app, st, d.n0);
+            if (lane == 0 && added) slc[l] += (unsigned long long)added;
+        }
+    }
+    app.flush();
+    __syncthreads();
+    if (lane < rl.nlev && slc[lane]) atomicAdd(rl.count[lane], slc[lane]);
+    if (stats) {
+        if constexpr (std::is_same<R, float>::value) wave_count(&stats[GEO_STAT_F32_TO_F64], st.fb);
+        wave_count(&stats[GEO_STAT_EXACT], st.ex);
+    }
+}
+
+// float32 form: 3 waves per SIMD (168 VGPRs; the cap spills 16 B per lane);
+// the float64 form keeps its registers (a cap spills it heavily)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8)))
+k_rows_levels_f32(DevMesh m, DevLevel d, RowLevels rl, int32_t* cnt, int2* pairs, int32_t* rank, int64_t cap,
+                  int64_t* d_pairs, uint64_t* stats) {
+    rows_levels_body<float>(m, d, rl, cnt, pairs, rank, cap, d_pairs, stats);
+}
+
+__global__ void __launch_bounds__(64) k_rows_levels_f64(DevMesh m, DevLevel d, RowLevels rl, int32_t* cnt, int2* pairs,
+                                                        int32_t* rank, int64_t cap, int64_t* d_pairs, uint64_t* stats) {
+    rows_levels_body<double>(m, d, rl, cnt, pairs, rank, cap, d_pairs, stats);
+}
+
+// zero the per-level counters and the shared pair counter
+__global__ void k_rows_levels_zero(RowLevels rl, int64_t* d_pairs) {
+    const int l = threadIdx.x;
+    if (l < rl.nlev) *rl.count[l] = 0ull;
+    if (l == 0) *d_pairs = 0;
+}
+
+// place the pairs of every level: the level of a pair is found from its key
+__global__ void k_rows_levels_scatter(const int2* pairs, const int32_t* rank, int64_t cap, const int64_t* d_pairs,
+                                      RowLevels rl) {
+    __shared__ int sbase[GEO_MAX_LEVELS + 1];
+    __shared__ const int32_t* soff[GEO_MAX_LEVELS];
+    __shared__ int32_t* sval[GEO_MAX_LEVELS];
+    __shared__ int64_t scap[GEO_MAX_LEVELS];
+    if (threadIdx.x < GEO_MAX_LEVELS + 1) sbase[threadIdx.x] = rl.base[threadIdx.x];
+    if (threadIdx.x < GEO_MAX_LEVELS) {
+        soff[threadIdx.x] = rl.off[threadIdx.x];
+        sval[threadIdx.x] = rl.val[threadIdx.x];
+        scap[threadIdx.x] = rl.cap[threadIdx.x];
+    }
+    __syncthreads();
+    const int64_t n0 = *d_pairs;
+    const int64_t n = n0 < cap ? n0 : cap;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int2 p = pairs[i];
+        int l = 0;
+        for (int q = 1; q < rl.nlev; q++) l += p.x >= sbase[q] ? 1 : 0;
+        const int64_t pos = (int64_t)soff[l][p.x - sbase[l]] + rank[i];
+        if (pos >= 0 && pos < scap[l]) sval[l][pos] = p.y;
     }
 }
 
@@ -538,13 +646,17 @@ __device__ bool tri_box_stage2(const double c[3], double hs, const SatTri& T) {
     return true;
 }
 
-__global__ void __launch_bounds__(64) k_links_pass1(DevMesh m, DevLevel d, int32_t* cnt, int2* pairs, int32_t* rank,
+// candidates of a triangle tested (and looked up) together
+constexpr int LINKS_U = 4;
+
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) k_links_pass1(DevMesh m, DevLevel d, int32_t* cnt, int2* pairs, int32_t* rank,
                                                     int64_t cap, int64_t* d_count) {
     __shared__ int2 sbuf[APP_BUF];
     Appender<true> app{sbuf, 0, pairs, rank, cap, d_count, cnt};
     const int L = d.level;
     const double h = ldexp(1.0, -L), bw = 4.0 * h;
-    const int nbx = (d.n0[0] >> 2) << L, nby = (d.n0[1] >> 2) << L, nbz = (d.n0[2] >> 2) << L;
+    const int nb0[3] = {d.n0[0] >> 2, d.n0[1] >> 2, d.n0[2] >> 2};
+    const int nbx = nb0[0] << L, nby = nb0[1] << L, nbz = nb0[2] << L;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m.nt; base += stride) {
         const int64_t t = base + threadIdx.x;
@@ -600,21 +712,36 @@ __global__ void __launch_bounds__(64) k_links_pass1(DevMesh m, DevLevel d, int32
             }
             for (int a = 0; a < 3; a++) c[a] = (b[a] + 0.5) * bw;
         };
-        // every candidate through both stages in turn (a triangle has a few
-        // candidates: its widened box spans one or two blocks per axis)
-        for (int64_t it = 0; __any(it < n); it++) {
-            bool has = false;
-            int key = 0;
-            if (it < n) {
-                int b[3];
-                double c[3];
-                centre(it, b, c);
-                if (tri_box_stage1(c, hs, T) && tri_box_stage2(c, hs, T)) {
-                    key = forest_lookup(d, b[0], b[1], b[2]);
-                    has = key >= 0;
+        // the candidates through both stages, LINKS_U at a time (a triangle
+        // has a few: its widened box spans one or two blocks per axis); the
+        // forest lookups of the LINKS_U candidates descend together, so their
+        // dependent loads overlap
+        for (int64_t it0 = 0; __any(it0 < n); it0 += LINKS_U) {
+            int bb[LINKS_U][3], idx[LINKS_U];
+#pragma unroll
+            for (int u = 0; u < LINKS_U; u++) {
+                idx[u] = -1;
+                bb[u][0] = bb[u][1] = bb[u][2] = 0;
+                if (it0 + u < n) {
+                    double c[3];
+                    centre(it0 + u, bb[u], c);
+                    if (tri_box_stage1(c, hs, T) && tri_box_stage2(c, hs, T))
+                        idx[u] = (bb[u][0] >> L) + nb0[0] * ((bb[u][1] >> L) + nb0[1] * (bb[u][2] >> L));
                 }
             }
-            app.add(has, key, (int32_t)t);
+            for (int l = 0; l < L; l++) {
+                int ch[LINKS_U];
+                const int sh = L - 1 - l;
+#pragma unroll
+                for (int u = 0; u < LINKS_U; u++) ch[u] = idx[u] >= 0 ? d.child[l][idx[u]] : -1;
+#pragma unroll
+                for (int u = 0; u < LINKS_U; u++)
+                    idx[u] = ch[u] < 0 ? -1
+                                       : ch[u] + (((bb[u][0] >> sh) & 1) | (((bb[u][1] >> sh) & 1) << 1) |
+                                                  (((bb[u][2] >> sh) & 1) << 2));
+            }
+#pragma unroll
+            for (int u = 0; u < LINKS_U; u++) app.add(idx[u] >= 0, idx[u], (int32_t)t);
         }
     }
     app.flush();
@@ -666,6 +793,36 @@ int launch_rows_pass1(const DevMesh& m, const DevLevel& d, int precision, int32_
     else
         k_rows_pass1<double><<<g, 64, 0, s>>>(m, d, cnt, pairs, rank, cap, d_count, d_stats);
     kt_record(GEO_KT_ROWS, s, true);
+    GEO_LAUNCH_CHECK();
+    return GEO_OK;
+}
+
+int launch_rows_levels(const DevMesh& m, const DevLevel& d, int precision, const RowLevels& rl, int32_t* cnt,
+                       int2* pairs, int32_t* rank, int64_t cap, int64_t* d_pairs, uint64_t* d_stats, hipStream_t s) {
+    if (m.nt == 0) return GEO_OK;
+    // grid caps measured on 7.2M triangles over levels 0..4: 16,384 workgroups
+    // for the float32 form (0.645 ms at 8,192), 2,048 for the float64 form
+    const unsigned g = grid_for(m.nt, 64, precision == GEO_PREC_F32_FALLBACK ? 16384 : 2048);
+    kt_record(GEO_KT_ROWS, s, false);
+    if (precision == GEO_PREC_F32_FALLBACK)
+        k_rows_levels_f32<<<g, 64, 0, s>>>(m, d, rl, cnt, pairs, rank, cap, d_pairs, d_stats);
+    else
+        k_rows_levels_f64<<<g, 64, 0, s>>>(m, d, rl, cnt, pairs, rank, cap, d_pairs, d_stats);
+    kt_record(GEO_KT_ROWS, s, true);
+    GEO_LAUNCH_CHECK();
+    return GEO_OK;
+}
+
+int launch_rows_levels_zero(const RowLevels& rl, int64_t* d_pairs, hipStream_t s) {
+    k_rows_levels_zero<<<1, 64, 0, s>>>(rl, d_pairs);
+    GEO_LAUNCH_CHECK();
+    return GEO_OK;
+}
+
+int launch_rows_levels_scatter(const int2* pairs, const int32_t* rank, int64_t cap, const int64_t* d_pairs,
+                               const RowLevels& rl, hipStream_t s) {
+    if (cap <= 0) return GEO_OK;
+    k_rows_levels_scatter<<<grid_for(cap, 256, 8192), 256, 0, s>>>(pairs, rank, cap, d_pairs, rl);
     GEO_LAUNCH_CHECK();
     return GEO_OK;
 }

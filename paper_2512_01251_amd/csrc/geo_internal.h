@@ -288,6 +288,22 @@ int geo_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 int geo_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
 int geo_sum_i32(const int32_t* in, int64_t n, int64_t* out, hipStream_t s);
 
+// ROWS bins of several levels built together (levels lmin .. lmin+nlev-1):
+// keys of level lmin+l start at base[l] in the joint key space; count, off,
+// val and cap are the levels' own bins.
+struct RowLevels {
+    int nlev, lmin;
+    int base[GEO_MAX_LEVELS + 1];
+    unsigned long long* count[GEO_MAX_LEVELS];
+    const int32_t* off[GEO_MAX_LEVELS];
+    int32_t* val[GEO_MAX_LEVELS];
+    int64_t cap[GEO_MAX_LEVELS];
+};
+int launch_rows_levels(const DevMesh& m, const DevLevel& d, int precision, const RowLevels& rl, int32_t* cnt,
+                       int2* pairs, int32_t* rank, int64_t cap, int64_t* d_pairs, uint64_t* d_stats, hipStream_t s);
+int launch_rows_levels_zero(const RowLevels& rl, int64_t* d_pairs, hipStream_t s);
+int launch_rows_levels_scatter(const int2* pairs, const int32_t* rank, int64_t cap, const int64_t* d_pairs,
+                               const RowLevels& rl, hipStream_t s);
 int launch_rows_pass1(const DevMesh& m, const DevLevel& d, int precision, int32_t* cnt,
                       int2* pairs, int32_t* rank, int64_t cap, int64_t* d_count, uint64_t* d_stats,
                       hipStream_t s);

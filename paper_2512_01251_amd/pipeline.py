@@ -1,8 +1,10 @@
 """Level-by-level embedding driver on top of the C entry points.
 
-For L = 0 .. L_f: ROWS bins and solid voxelization of level L; for L < L_f
-the refinement flags produce the blocks of level L+1 (Methodology, overview:
-voxelization and refinement run level by level, top-down).  On L_f the LINKS
+ROWS bins of levels 0 .. L_f first (one pass over the triangles; they do not
+depend on the blocks); then for L = 0 .. L_f the solid voxelization of level
+L, and for L < L_f the refinement flags produce the blocks of level L+1
+(Methodology, overview: voxelization and refinement run level by level,
+top-down).  On L_f the LINKS
 bins and the cut-link table follow.  The host only sizes buffers: it waits for
 the next level's block count after each refinement, and for all bin and link
 counts once at the end (a pass that overflowed a buffer is redone with larger
@@ -14,9 +16,10 @@ from dataclasses import dataclass, field
 
 import torch
 
-from . import (GEO_BINS_LINKS, GEO_BINS_ROWS, GEO_CALL_BINS_LINKS, GEO_CALL_BINS_ROWS, GEO_CALL_CUTLINKS,
+from . import (GEO_BINS_LINKS, GEO_BINS_ROWS, GEO_CALL_BINS_LINKS, GEO_CALL_BINS_ROWS, GEO_CALL_BINS_ROWS_LEVELS,
+               GEO_CALL_CUTLINKS,
                GEO_CALL_LINKS_DENSE, GEO_CALL_REFINE, GEO_NSTATS, GEO_STAT_CONTRACT, GEO_PREC_F32_FALLBACK, GEO_PREC_F64,
-               geo_build_bins, geo_cutlinks, geo_cutlinks_backward, geo_level0_blocks, geo_links_dense, geo_nprop,
+               geo_build_bins, geo_build_row_bins_levels, geo_cutlinks, geo_cutlinks_backward, geo_level0_blocks, geo_links_dense, geo_nprop,
                geo_refine_flags, geo_solid_change, geo_voxelize, geo_workspace_size, make_bins, make_level,
                make_mesh)
 
@@ -122,20 +125,13 @@ class Embedder:
         child_maps = []
         rows = None
 
-        def row_bins(L, lvd):
-            # ROWS bins depend on the level, not on its blocks: the next level's
-            # are enqueued before the host waits for that level's block count
-            nkeys = (n0[1] << L) * (n0[2] << L)
-            key = ("rows", L)
-            cap = self.caps.get(key, max(4096, 2 * mesh.nt))
-            off, val = self._bins(mesh, lvd, GEO_BINS_ROWS, prec, nkeys, stats, cap, cnt(L), f"rows{L}")
-            return nkeys, key, cap, off, val
-
-        ahead = row_bins(0, make_level(n0, 0, bcoord, child_maps))
+        # ROWS bins depend on the level, not on its blocks: those of every
+        # level are built first, in one pass over the triangles
+        row_bins = self._row_bins_levels(mesh, n0, lf, prec, stats, cnt)
         for L in range(lf + 1):
             lvd = make_level(n0, L, bcoord, child_maps)
             rec = Level(L, bcoord)
-            nkeys, key, cap, rec.rows_off, val = ahead
+            nkeys, key, cap, rec.rows_off, val = row_bins[L]
             checks.append((L, cap, key, lambda c, rec=rec, val=val: setattr(rec, "rows_val", val[:c])))
             rows = make_bins(GEO_BINS_ROWS, nkeys, rec.rows_off, val, cap, cnt(L))
             rec.rows_val = val
@@ -157,8 +153,6 @@ class Embedder:
                 counted = torch.cuda.Event()
                 counted.record()
                 child_maps.append(rec.child_map)
-                empty = torch.empty((0, 3), dtype=torch.int32, device=dev)
-                ahead = row_bins(L + 1, make_level(n0, L + 1, empty, child_maps))
                 counted.synchronize()
                 nchild = int(self._host_n[0])
                 bcoord = child[:nchild]
@@ -186,6 +180,25 @@ class Embedder:
         for i, cap, key, apply in checks:
             apply(counts[i])
         out.stats = stats
+        return out
+
+    def _row_bins_levels(self, mesh, n0, lf, prec, stats, cnt):
+        """ROWS bins of levels 0..lf with one C call: per level (nkeys,
+        capacity key, capacity, off, val); level L counts into cnt(L)."""
+        dev = self.device
+        out, bins = [], []
+        for L in range(lf + 1):
+            nkeys = (n0[1] << L) * (n0[2] << L)
+            key = ("rows", L)
+            cap = self.caps.get(key, max(4096, 2 * mesh.nt))
+            off = torch.empty(nkeys + 1, dtype=torch.int32, device=dev)
+            val = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+            bins.append(make_bins(GEO_BINS_ROWS, nkeys, off, val, cap, cnt(L)))
+            out.append((nkeys, key, cap, off, val))
+        ws = self._workspace(geo_workspace_size(GEO_CALL_BINS_ROWS_LEVELS, sum(o[0] for o in out),
+                                                sum(o[2] for o in out)))
+        with self._timed("rows"):
+            geo_build_row_bins_levels(mesh, n0, 0, prec, bins, stats, ws)
         return out
 
     def _bins(self, mesh, lvd, kind, prec, nkeys, stats, cap, d_count, tname):

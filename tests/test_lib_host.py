@@ -307,3 +307,41 @@ def test_noalloc_cutlinks_rejects_oversize_requests_before_any_device_call(geo):
                                 None, 16, None, None, None, None, None, None, None)
     assert rc == geo.GEO_ERR_ARG
     assert geo.geo_workspace_size(geo.GEO_CALL_CUTLINKS, 4096, 100000) <= geo.GEO_NOALLOC_SCRATCH_BYTES
+
+
+def test_row_bins_levels_arguments_are_checked_on_the_host(geo):
+    """geo_build_row_bins_levels validates the level range, each level's
+    descriptor and the workspace before any device call (fake device
+    addresses are never dereferenced: every case here returns first)."""
+    L = geo.lib()
+    mesh = geo.geo_mesh(0, 0, geo.GEO_F32, None, None)
+    n0 = (C.c_int32 * 3)(32, 32, 32)
+    fake = 1 << 20
+
+    def bins_for(levels, cap=64, counts=None):
+        arr = (geo.geo_bins * len(levels))()
+        for i, lev in enumerate(levels):
+            arr[i] = geo.geo_bins(geo.GEO_BINS_ROWS, (32 << lev) * (32 << lev), fake, fake, cap,
+                                  fake + 256 * i if counts is None else counts[i])
+        return arr
+
+    f32 = geo.GEO_PREC_F32_FALLBACK
+    ok = bins_for([0, 1, 2])
+    nk = sum((32 << l) ** 2 for l in range(3))
+    need = geo.geo_workspace_size(geo.GEO_CALL_BINS_ROWS_LEVELS, nk, 3 * 64)
+    assert need > geo.geo_workspace_size(geo.GEO_CALL_BINS_ROWS, nk, 3 * 64)
+    call = lambda lmin, nlev, arr, prec=f32, ws_bytes=need, mesh=mesh, n0=n0: L.geo_build_row_bins_levels(
+        C.byref(mesh), n0, lmin, nlev, prec, arr, None, C.c_void_p(fake), ws_bytes, None)
+    assert call(0, 0, ok) == geo.GEO_ERR_ARG                       # no level
+    assert call(-1, 3, ok) == geo.GEO_ERR_ARG
+    assert call(10, 3, bins_for([10, 11, 12])) == geo.GEO_ERR_ARG  # beyond GEO_MAX_LEVELS
+    assert call(0, 3, ok, prec=7) == geo.GEO_ERR_ARG
+    assert call(1, 3, ok) == geo.GEO_ERR_ARG                       # nkeys of levels 0..2 given for 1..3
+    assert call(0, 3, bins_for([0, 1, 2], counts=[fake, fake, fake + 256])) == geo.GEO_ERR_ARG  # shared counter
+    bad = bins_for([0, 1, 2])
+    bad[1].kind = geo.GEO_BINS_LINKS
+    assert call(0, 3, bad) == geo.GEO_ERR_ARG
+    big = (C.c_int32 * 3)(4096, 4096, 4096)                          # 4096 * 2^3 > GEO_MAX_RES
+    assert call(0, 4, bins_for([0, 1, 2, 3]), n0=big) == geo.GEO_ERR_ARG
+    assert call(0, 3, ok, ws_bytes=need - 1) == geo.GEO_ERR_WORKSPACE
+    assert L.geo_build_row_bins_levels(C.byref(mesh), None, 0, 3, f32, ok, None, None, 0, None) == geo.GEO_ERR_ARG
