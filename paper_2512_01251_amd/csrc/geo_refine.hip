@@ -23,14 +23,71 @@ __device__ __forceinline__ void nbr_offset(int k, int& dx, int& dy, int& dz) {
     dz = kk / 9 - 1;
 }
 
+// 26-neighbour indices (forest_lookup values: index, -1 missing, -2 outside
+// the domain).  On levels L >= 1 the 26 neighbours have at most 8 distinct
+// parents, the 2x2x2 parents from (b-1) >> 1 to (b+1) >> 1 on each axis: the
+// first-child indices of those 8 are found by 8 descents of the forest run
+// side by side (their dependent loads overlap), and each neighbour is its
+// parent's first child plus its octant, with no further load.
 __global__ void k_ref_nbr(DevLevel d, const uint64_t* solid, int32_t* nbr, uint8_t* flags) {
     const int64_t nb = d.nblocks;
+    const int L = d.level;
+    const int nb0[3] = {d.n0[0] >> 2, d.n0[1] >> 2, d.n0[2] >> 2};
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
-        const int bx = d.bcoord[3 * b], by = d.bcoord[3 * b + 1], bz = d.bcoord[3 * b + 2];
-        for (int k = 0; k < 26; k++) {
-            int dx, dy, dz;
-            nbr_offset(k, dx, dy, dz);
-            nbr[(int64_t)k * nb + b] = forest_lookup(d, bx + dx, by + dy, bz + dz);
+        const int bc[3] = {d.bcoord[3 * b], d.bcoord[3 * b + 1], d.bcoord[3 * b + 2]};
+        if (L == 0) {  // the dense root grid: no loads
+            for (int k = 0; k < 26; k++) {
+                int dx, dy, dz;
+                nbr_offset(k, dx, dy, dz);
+                nbr[(int64_t)k * nb + b] = forest_lookup(d, bc[0] + dx, bc[1] + dy, bc[2] + dz);
+            }
+        } else {
+            int p0[3];  // lowest parent coordinate per axis (level L-1)
+            for (int a = 0; a < 3; a++) p0[a] = (bc[a] - 1) >> 1;
+            int idx[8];
+            bool inside[8];
+#pragma unroll
+            for (int s = 0; s < 8; s++) {
+                const int p[3] = {p0[0] + (s & 1), p0[1] + ((s >> 1) & 1), p0[2] + (s >> 2)};
+                inside[s] = true;
+                for (int a = 0; a < 3; a++)
+                    if (p[a] < 0 || p[a] >= (nb0[a] << (L - 1))) inside[s] = false;
+                idx[s] = inside[s] ? (p[0] >> (L - 1)) + nb0[0] * ((p[1] >> (L - 1)) + nb0[1] * (p[2] >> (L - 1)))
+                                   : -1;
+            }
+            // descend to level L-1, then the parent's first child on level L
+            for (int l = 0; l < L; l++) {
+                int c[8];
+#pragma unroll
+                for (int s = 0; s < 8; s++) c[s] = idx[s] >= 0 ? d.child[l][idx[s]] : -1;
+                const int sh = L - 2 - l;
+#pragma unroll
+                for (int s = 0; s < 8; s++) {
+                    if (l == L - 1 || c[s] < 0) {
+                        idx[s] = c[s];
+                    } else {
+                        const int p[3] = {p0[0] + (s & 1), p0[1] + ((s >> 1) & 1), p0[2] + (s >> 2)};
+                        idx[s] = c[s] + (((p[0] >> sh) & 1) | (((p[1] >> sh) & 1) << 1) | (((p[2] >> sh) & 1) << 2));
+                    }
+                }
+            }
+            for (int k = 0; k < 26; k++) {
+                int dv[3];
+                nbr_offset(k, dv[0], dv[1], dv[2]);
+                int n[3], s = 0;
+                bool out = false;
+                for (int a = 0; a < 3; a++) {
+                    n[a] = bc[a] + dv[a];
+                    if (n[a] < 0 || n[a] >= (nb0[a] << L)) out = true;
+                    s |= ((n[a] >> 1) - p0[a]) << a;
+                }
+                int r = -2;
+                if (!out) {
+                    const int fc = idx[s];
+                    r = fc < 0 ? -1 : fc + ((n[0] & 1) | ((n[1] & 1) << 1) | ((n[2] & 1) << 2));
+                }
+                nbr[(int64_t)k * nb + b] = r;
+            }
         }
         flags[b] = solid[b] != 0ull ? F_S : 0;
     }
