@@ -122,9 +122,9 @@ def _ptr(t):
 
 
 def _stream(stream):
-    if stream is None:
+    if stream is None:  # the current stream of the current device
         import torch
-        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        return C.c_void_p(torch._C._cuda_getCurrentRawStream(torch.cuda.current_device()))
     return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
 
 

@@ -12,6 +12,8 @@ buffers; every kernel clamps to the capacity it is given).
 """
 from __future__ import annotations
 
+import time
+
 from dataclasses import dataclass, field
 
 import torch
@@ -24,6 +26,7 @@ from . import (GEO_BINS_LINKS, GEO_BINS_ROWS, GEO_CALL_BINS_LINKS, GEO_CALL_BINS
                make_mesh)
 
 PRECISIONS = {"f64": GEO_PREC_F64, "f32": GEO_PREC_F32_FALLBACK}
+POLL_S = 0.05   # longest poll of a pinned count before the event's wait takes over
 
 
 @dataclass
@@ -73,6 +76,8 @@ class Embedder:
         # pinned host word for the per-level block count (read without a
         # stream-wide wait)
         self._host_n = torch.zeros(1, dtype=torch.int64, pin_memory=self.device.type == "cuda")
+        self._host_np = self._host_n.numpy()
+        self._poll = self.device.type == "cuda"
         self.events = None   # list of (name, start_event, end_event) when timing
 
     # -- helpers ---------------------------------------------------------------
@@ -80,6 +85,23 @@ class Embedder:
         if self.ws.numel() < nbytes:
             self.ws = torch.empty(int(nbytes * 1.25) + 4096, dtype=torch.uint8, device=self.device)
         return self.ws
+
+    def _wait_count(self, ev) -> int:
+        """The count copied into the pinned host word (set to -1 before the
+        copy): polled, since the copy's landing is seen sooner than the
+        event's wait returns; after POLL_S without it (or once that has
+        happened) the event's wait is used."""
+        h = self._host_np
+        if self._poll:
+            t_end = time.perf_counter() + POLL_S
+            while h[0] < 0:
+                if time.perf_counter() > t_end:
+                    self._poll = False
+                    break
+            if h[0] >= 0:
+                return int(h[0])
+        ev.synchronize()
+        return int(h[0])
 
     def _timed(self, name):
         if self.events is None:
@@ -128,35 +150,44 @@ class Embedder:
         # ROWS bins depend on the level, not on its blocks: those of every
         # level are built first, in one pass over the triangles
         row_bins = self._row_bins_levels(mesh, n0, lf, prec, stats, cnt)
+        # Each level's voxelization is launched as soon as its block count is
+        # known: the next level's descriptor and solid buffer (at the capacity
+        # 8 nb) are made while the GPU refines, the rest of a level's buffers
+        # after its voxelization is enqueued.
+        lvd = make_level(n0, 0, bcoord, child_maps)
+        solid = torch.empty(nb0, dtype=torch.int64, device=dev)
+        with self._timed("voxelize0"):
+            geo_voxelize(lvd, row_bins[0][5], solid)
         for L in range(lf + 1):
-            lvd = make_level(n0, L, bcoord, child_maps)
+            nb = lvd.nblocks
             rec = Level(L, bcoord)
-            nkeys, key, cap, rec.rows_off, val = row_bins[L]
-            checks.append((L, cap, key, lambda c, rec=rec, val=val: setattr(rec, "rows_val", val[:c])))
-            rows = make_bins(GEO_BINS_ROWS, nkeys, rec.rows_off, val, cap, cnt(L))
+            rec.solid = solid
+            nkeys, key, cap, rec.rows_off, val, rows = row_bins[L]
             rec.rows_val = val
-            rec.solid = torch.empty(lvd.nblocks, dtype=torch.int64, device=dev)
-            with self._timed(f"voxelize{L}"):
-                geo_voxelize(lvd, rows, rec.solid)
-            if L < lf:
-                nb = lvd.nblocks
-                rec.bclass = torch.empty(nb, dtype=torch.uint8, device=dev)
-                rec.refine = torch.empty(nb, dtype=torch.uint8, device=dev)
-                rec.child_map = torch.empty(nb, dtype=torch.int32, device=dev)
-                child = torch.empty((8 * nb, 3), dtype=torch.int32, device=dev)
-                d_n = cnt(lf + 1 + L)
-                ws = self._workspace(geo_workspace_size(GEO_CALL_REFINE, nb, 0))
-                with self._timed(f"refine{L}"):
-                    geo_refine_flags(lvd, rec.solid, n_prop, rec.bclass, rec.refine, rec.child_map, child,
-                                     d_n, ws)
-                self._host_n.copy_(d_n, non_blocking=True)
-                counted = torch.cuda.Event()
-                counted.record()
-                child_maps.append(rec.child_map)
-                counted.synchronize()
-                nchild = int(self._host_n[0])
-                bcoord = child[:nchild]
+            checks.append((L, cap, key, lambda c, rec=rec, val=val: setattr(rec, "rows_val", val[:c])))
             out.levels.append(rec)
+            if L == lf:
+                break
+            rec.bclass = torch.empty(nb, dtype=torch.uint8, device=dev)
+            rec.refine = torch.empty(nb, dtype=torch.uint8, device=dev)
+            rec.child_map = torch.empty(nb, dtype=torch.int32, device=dev)
+            child = torch.empty((8 * nb, 3), dtype=torch.int32, device=dev)
+            ws = self._workspace(geo_workspace_size(GEO_CALL_REFINE, nb, 0))
+            d_n = cnt(lf + 1 + L)
+            with self._timed(f"refine{L}"):
+                geo_refine_flags(lvd, rec.solid, n_prop, rec.bclass, rec.refine, rec.child_map, child, d_n, ws)
+            self._host_np[0] = -1
+            self._host_n.copy_(d_n, non_blocking=True)
+            counted = torch.cuda.Event()
+            counted.record()
+            child_maps.append(rec.child_map)
+            nxt = make_level(n0, L + 1, child, child_maps)
+            solid_next = torch.empty(8 * nb, dtype=torch.int64, device=dev)
+            nchild = self._wait_count(counted)
+            nxt.nblocks = nchild
+            with self._timed(f"voxelize{L + 1}"):
+                geo_voxelize(nxt, row_bins[L + 1][5], solid_next)
+            lvd, bcoord, solid = nxt, child[:nchild], solid_next[:nchild]
         if with_links:
             out.links = self._cutlinks(mesh, n0, lf, out.levels[-1], child_maps, rows, lattice, prec, stats,
                                        with_mask, cnt(2 * lf + 1), cnt(2 * lf + 2), checks)
@@ -184,17 +215,25 @@ class Embedder:
 
     def _row_bins_levels(self, mesh, n0, lf, prec, stats, cnt):
         """ROWS bins of levels 0..lf with one C call: per level (nkeys,
-        capacity key, capacity, off, val); level L counts into cnt(L)."""
+        capacity key, capacity, off, val, descriptor); level L counts into
+        cnt(L)."""
         dev = self.device
-        out, bins = [], []
-        for L in range(lf + 1):
+        out, bins, spans = [], [], []
+        pos = 0
+        for L in range(lf + 1):  # one allocation, the arrays 256-byte aligned
             nkeys = (n0[1] << L) * (n0[2] << L)
             key = ("rows", L)
             cap = self.caps.get(key, max(4096, 2 * mesh.nt))
-            off = torch.empty(nkeys + 1, dtype=torch.int32, device=dev)
-            val = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+            o = pos
+            pos = (pos + nkeys + 1 + 63) // 64 * 64
+            v = pos
+            pos = (pos + max(cap, 1) + 63) // 64 * 64
+            spans.append((nkeys, key, cap, o, v))
+        buf = torch.empty(pos, dtype=torch.int32, device=dev)
+        for L, (nkeys, key, cap, o, v) in enumerate(spans):
+            off, val = buf[o:o + nkeys + 1], buf[v:v + max(cap, 1)]
             bins.append(make_bins(GEO_BINS_ROWS, nkeys, off, val, cap, cnt(L)))
-            out.append((nkeys, key, cap, off, val))
+            out.append((nkeys, key, cap, off, val, bins[-1]))
         ws = self._workspace(geo_workspace_size(GEO_CALL_BINS_ROWS_LEVELS, sum(o[0] for o in out),
                                                 sum(o[2] for o in out)))
         with self._timed("rows"):
