@@ -654,7 +654,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
     __shared__ int2 sbuf[APP_BUF];
     Appender<true> app{sbuf, 0, pairs, rank, cap, d_count, cnt};
     const int L = d.level;
-    const double h = ldexp(1.0, -L), bw = 4.0 * h;
+    const double h = ldexp(1.0, -L), bw = 4.0 * h, ibw = ldexp(1.0, L - 2);  // 1 / bw, exact
     const int nb0[3] = {d.n0[0] >> 2, d.n0[1] >> 2, d.n0[2] >> 2};
     const int nbx = nb0[0] << L, nby = nb0[1] << L, nbz = nb0[2] << L;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -688,8 +688,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
                 // [mn, mx] iff (mn - 4.5h) / bw <= b <= (mx + h/2) / bw (the
                 // roundings are monotone and bw is a power of two; the 1e-7
                 // only widens the range)
-                lo[a] = (int)ceil((mn - 4.5 * h) / bw - 1e-7);
-                hi[a] = (int)floor((mx + 0.5 * h) / bw + 1e-7);
+                lo[a] = (int)ceil((mn - 4.5 * h) * ibw - 1e-7);
+                hi[a] = (int)floor((mx + 0.5 * h) * ibw + 1e-7);
                 lo[a] = lo[a] < 0 ? 0 : lo[a];
                 hi[a] = hi[a] > nb[a] - 1 ? nb[a] - 1 : hi[a];
             }
@@ -697,36 +697,32 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
         const int sx = hi[0] - lo[0] + 1, sy = hi[1] - lo[1] + 1, sz = hi[2] - lo[2] + 1;
         const int64_t n = (sx > 0 && sy > 0 && sz > 0) ? (int64_t)sx * sy * sz : 0;
         const double hs = (0.5 * bw + 0.5 * h) * (1.0 + 1e-9);
-        // candidate block it of the triangle: box [4bh - h/2, 4(b+1)h + h/2]
-        // reached by the block's links, plus a relative margin
-        auto centre = [&](int64_t it, int b[3], double c[3]) {
-            if (n <= INT32_MAX) {  // 32-bit division where the range allows it
-                const unsigned u = (unsigned)it, usx = (unsigned)sx, q = u / usx;
-                b[0] = lo[0] + (int)(u - q * usx);
-                b[1] = lo[1] + (int)(q % (unsigned)sy);
-                b[2] = lo[2] + (int)(q / (unsigned)sy);
-            } else {
-                b[0] = lo[0] + (int)(it % sx);
-                b[1] = lo[1] + (int)((it / sx) % sy);
-                b[2] = lo[2] + (int)(it / ((int64_t)sx * sy));
-            }
-            for (int a = 0; a < 3; a++) c[a] = (b[a] + 0.5) * bw;
-        };
-        // the candidates through both stages, LINKS_U at a time (a triangle
-        // has a few: its widened box spans one or two blocks per axis); the
-        // forest lookups of the LINKS_U candidates descend together, so their
-        // dependent loads overlap
+        // candidate block: box [4bh - h/2, 4(b+1)h + h/2] reached by the
+        // block's links, plus a relative margin.  The candidates through both
+        // stages, LINKS_U at a time (a triangle has a few: its widened box
+        // spans one or two blocks per axis), enumerated x fastest by a cursor;
+        // the forest lookups of the LINKS_U candidates descend together, so
+        // their dependent loads overlap.
+        int cur[3] = {lo[0], lo[1], lo[2]};
         for (int64_t it0 = 0; __any(it0 < n); it0 += LINKS_U) {
             int bb[LINKS_U][3], idx[LINKS_U];
 #pragma unroll
             for (int u = 0; u < LINKS_U; u++) {
                 idx[u] = -1;
-                bb[u][0] = bb[u][1] = bb[u][2] = 0;
+                bb[u][0] = cur[0];
+                bb[u][1] = cur[1];
+                bb[u][2] = cur[2];
                 if (it0 + u < n) {
-                    double c[3];
-                    centre(it0 + u, bb[u], c);
+                    const double c[3] = {(cur[0] + 0.5) * bw, (cur[1] + 0.5) * bw, (cur[2] + 0.5) * bw};
                     if (tri_box_stage1(c, hs, T) && tri_box_stage2(c, hs, T))
-                        idx[u] = (bb[u][0] >> L) + nb0[0] * ((bb[u][1] >> L) + nb0[1] * (bb[u][2] >> L));
+                        idx[u] = (cur[0] >> L) + nb0[0] * ((cur[1] >> L) + nb0[1] * (cur[2] >> L));
+                }
+                if (++cur[0] > hi[0]) {
+                    cur[0] = lo[0];
+                    if (++cur[1] > hi[1]) {
+                        cur[1] = lo[1];
+                        ++cur[2];
+                    }
                 }
             }
             for (int l = 0; l < L; l++) {
