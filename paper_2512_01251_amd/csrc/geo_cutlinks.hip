@@ -62,80 +62,121 @@ __device__ __forceinline__ uint32_t lattice_dirs(int lattice) {
     return m;
 }
 
-// 6-bit solid vector of centres x0-1 .. x0+4 of one row line
-__device__ __forceinline__ unsigned halo_bits(const int32_t* off, const int32_t* val, int64_t cap, int64_t line,
-                                              int xm1, int nx) {
-    int64_t e0 = off[line], e1 = off[line + 1];
-    if (e1 > cap) e1 = cap;
-    if (e0 < 0) e0 = 0;
-    unsigned par = 0, surf = 0;
-    for (int64_t e = e0; e < e1; e += 4) {
-        // four independent loads in flight before the first use
-        int32_t v4[4];
+// 6-bit solid vectors of centres x0-1 .. x0+4 of row lines, from the ROWS
+// bins: parity of the crossings ahead, or'ed with the on-surface intervals
+
+// fold entries v[0..n-1] of a halo line (centres xm1 .. xm1+5) into par / surf
+__device__ __forceinline__ void fold_halo(const int32_t* v4, int64_t n, int xm1, unsigned& par, unsigned& surf) {
 #pragma unroll
-        for (int i = 0; i < 4; i++) v4[i] = e + i < e1 ? val[e + i] : 0;
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-            if (e + i >= e1) break;
-            const int32_t v = v4[i];
-            if (v >= 0) {
-                int n = v - xm1;
-                n = n < 0 ? 0 : (n > 6 ? 6 : n);
-                par ^= (1u << n) - 1u;
-            } else {
-                int a = (v & 0x7fff) - xm1, b = ((v >> 15) & 0x7fff) - xm1;
-                a = a < 0 ? 0 : a;
-                b = b > 5 ? 5 : b;
-                if (a <= b) surf |= ((1u << (b + 1)) - 1u) & ~((1u << a) - 1u);
-            }
+    for (int i = 0; i < 4; i++) {
+        if (i >= n) break;
+        const int32_t v = v4[i];
+        if (v >= 0) {
+            int c = v - xm1;
+            c = c < 0 ? 0 : (c > 6 ? 6 : c);
+            par ^= (1u << c) - 1u;
+        } else {
+            int a = (v & 0x7fff) - xm1, b = ((v >> 15) & 0x7fff) - xm1;
+            a = a < 0 ? 0 : a;
+            b = b > 5 ? 5 : b;
+            if (a <= b) surf |= ((1u << (b + 1)) - 1u) & ~((1u << a) - 1u);
         }
     }
-    unsigned r = (par | surf) & 0x3fu;
-    // centres outside the domain are fluid
-    for (int p = 0; p < 6; p++) {
-        const int x = xm1 + p;
-        if (x < 0 || x >= nx) r &= ~(1u << p);
-    }
-    return r;
 }
 
-// link masks of block b: lanes 0..35 classify the 36 halo row lines into
-// LDS, then lane t forms the mask of cell t (0 for solid cells)
-__device__ __forceinline__ uint32_t block_link_mask(const DevLevel& d, const int32_t* off, const int32_t* val,
-                                                    int64_t cap, uint32_t dirs, int64_t b, unsigned* halo) {
+// halo_bits of two lines (of two blocks) with their loads in flight together:
+// both offset pairs, then the first four entries of both lines
+__device__ __forceinline__ void halo_bits2(const int32_t* off, const int32_t* val, int64_t cap, bool ha, int64_t la,
+                                           int xa, bool hb, int64_t lb, int xb, int nx, unsigned& ra, unsigned& rb) {
+    int64_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+    if (ha) { a0 = off[la]; a1 = off[la + 1]; }
+    if (hb) { b0 = off[lb]; b1 = off[lb + 1]; }
+    if (a1 > cap) a1 = cap;
+    if (a0 < 0) a0 = 0;
+    if (b1 > cap) b1 = cap;
+    if (b0 < 0) b0 = 0;
+    int32_t va[4], vb[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        va[i] = a0 + i < a1 ? val[a0 + i] : 0;
+        vb[i] = b0 + i < b1 ? val[b0 + i] : 0;
+    }
+    unsigned pa = 0, sa = 0, pb = 0, sb = 0;
+    fold_halo(va, a1 - a0, xa, pa, sa);
+    fold_halo(vb, b1 - b0, xb, pb, sb);
+    for (int64_t e = a0 + 4; e < a1; e += 4) {  // lines with more than four entries
+#pragma unroll
+        for (int i = 0; i < 4; i++) va[i] = e + i < a1 ? val[e + i] : 0;
+        fold_halo(va, a1 - e, xa, pa, sa);
+    }
+    for (int64_t e = b0 + 4; e < b1; e += 4) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) vb[i] = e + i < b1 ? val[e + i] : 0;
+        fold_halo(vb, b1 - e, xb, pb, sb);
+    }
+    ra = (pa | sa) & 0x3fu;
+    rb = (pb | sb) & 0x3fu;
+    // centres outside the domain are fluid
+    for (int p = 0; p < 6; p++) {
+        if (xa + p < 0 || xa + p >= nx) ra &= ~(1u << p);
+        if (xb + p < 0 || xb + p >= nx) rb &= ~(1u << p);
+    }
+}
+
+// link masks of blocks ba and bb (bb < 0: none) together: lanes 0..35
+// classify the 36 halo row lines of both into LDS, then lane t forms the
+// masks of cell t of both
+__device__ __forceinline__ void block_link_mask2(const DevLevel& d, const int32_t* off, const int32_t* val, int64_t cap,
+                                                 uint32_t dirs, int64_t ba, int64_t bb, unsigned* halo, uint32_t& ma,
+                                                 uint32_t& mb) {
     const int L = d.level;
     const int nx = d.n0[0] << L, ny = d.n0[1] << L, nz = d.n0[2] << L;
     const int lane = threadIdx.x;
-    const int bx = d.bcoord[3 * b], by = d.bcoord[3 * b + 1], bz = d.bcoord[3 * b + 2];
+    const bool two = bb >= 0;
+    const int ax = d.bcoord[3 * ba], ay = d.bcoord[3 * ba + 1], az = d.bcoord[3 * ba + 2];
+    int bx = 0, by = 0, bz = 0;
+    if (two) {
+        bx = d.bcoord[3 * bb];
+        by = d.bcoord[3 * bb + 1];
+        bz = d.bcoord[3 * bb + 2];
+    }
     __syncthreads();
     if (lane < 36) {
         const int J = lane % 6 - 1, K = lane / 6 - 1;
-        const int j = 4 * by + J, k = 4 * bz + K;
-        unsigned bits = 0;
-        if (j >= 0 && j < ny && k >= 0 && k < nz)
-            bits = halo_bits(off, val, cap, (int64_t)j + (int64_t)ny * k, 4 * bx - 1, nx);
-        halo[lane] = bits;
+        const int ja = 4 * ay + J, ka = 4 * az + K, jb = 4 * by + J, kb = 4 * bz + K;
+        const bool ha = ja >= 0 && ja < ny && ka >= 0 && ka < nz;
+        const bool hb = two && jb >= 0 && jb < ny && kb >= 0 && kb < nz;
+        unsigned ra, rb;
+        halo_bits2(off, val, cap, ha, (int64_t)ja + (int64_t)ny * ka, 4 * ax - 1, hb, (int64_t)jb + (int64_t)ny * kb,
+                   4 * bx - 1, nx, ra, rb);
+        halo[lane] = ha ? ra : 0u;
+        halo[36 + lane] = hb ? rb : 0u;
     }
     __syncthreads();
     const int I = lane & 3, J = (lane >> 2) & 3, K = lane >> 4;
-    // 27-bit neighbourhood word, bit (cx+1) + 3 (cy+1) + 9 (cz+1)
-    uint32_t nb = 0;
+    // 27-bit neighbourhood words, bit (cx+1) + 3 (cy+1) + 9 (cz+1)
+    uint32_t na = 0, nb = 0;
 #pragma unroll
     for (int dz = 0; dz < 3; dz++)
 #pragma unroll
-        for (int dy = 0; dy < 3; dy++) nb |= ((halo[(J + dy) + 6 * (K + dz)] >> I) & 7u) << (3 * dy + 9 * dz);
-    return ((nb >> 13) & 1u) ? 0u : (nb & dirs);
+        for (int dy = 0; dy < 3; dy++) {
+            const int h = (J + dy) + 6 * (K + dz);
+            na |= ((halo[h] >> I) & 7u) << (3 * dy + 9 * dz);
+            nb |= ((halo[36 + h] >> I) & 7u) << (3 * dy + 9 * dz);
+        }
+    ma = ((na >> 13) & 1u) ? 0u : (na & dirs);
+    mb = ((nb >> 13) & 1u) ? 0u : (nb & dirs);
 }
 
 __global__ void __launch_bounds__(64) k_cl_mask(DevLevel d, const int32_t* off, const int32_t* val, int64_t cap,
                                                 const int32_t* loff, int lattice, uint32_t* wmask, int zero_fill,
                                                 int32_t* blk_cnt) {
-    __shared__ unsigned halo[36];
+    __shared__ unsigned halo[72];
     const uint32_t dirs = lattice_dirs(lattice);
     const int lane = threadIdx.x;
     const int64_t nchunks = (d.nblocks + 63) / 64;
     // chunks of 64 blocks: one coalesced read of their candidate counts, then
-    // only the blocks with candidates are classified, one per wave step
+    // only the blocks with candidates are classified, two per wave step
     for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
         const int64_t b0 = ch * 64;
         const int64_t bl = b0 + lane;
@@ -148,13 +189,26 @@ __global__ void __launch_bounds__(64) k_cl_mask(DevLevel d, const int32_t* off, 
         while (todo) {  // uniform
             const int i = __ffsll(todo) - 1;
             todo &= todo - 1;
-            const int64_t b = b0 + i;
-            const uint32_t m = block_link_mask(d, off, val, cap, dirs, b, halo);
-            wmask[64 * b + lane] = m;
-            int c = __popc(m);
+            int j = -1;
+            if (todo) {
+                j = __ffsll(todo) - 1;
+                todo &= todo - 1;
+            }
+            const int64_t ba = b0 + i, bb = j >= 0 ? b0 + j : -1;
+            uint32_t ma, mb;
+            block_link_mask2(d, off, val, cap, dirs, ba, bb, halo, ma, mb);
+            wmask[64 * ba + lane] = ma;
+            if (bb >= 0) wmask[64 * bb + lane] = mb;
+            int ca = __popc(ma), cb = __popc(mb);
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-            if (lane == 0) blk_cnt[b] = c;
+            for (int o = 32; o > 0; o >>= 1) {
+                ca += __shfl_xor(ca, o, 64);
+                cb += __shfl_xor(cb, o, 64);
+            }
+            if (lane == 0) {
+                blk_cnt[ba] = ca;
+                if (bb >= 0) blk_cnt[bb] = cb;
+            }
         }
         if (zero_fill) {  // the caller's mask: every block is written
             unsigned long long empty = __ballot(inb && !has);
