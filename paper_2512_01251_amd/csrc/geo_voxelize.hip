@@ -9,20 +9,21 @@
 // the block set of a level cannot leave cells unfilled.
 //
 // Layout: a wave handles 4 blocks, 16 lanes per block, one lane per row line
-// (J, K) of the block; each lane produces the 4 flags of its line and four
-// ballots assemble the 64-bit block mask (bit t = I + 4 J + 16 K).
+// (J, K) of the block; each lane produces the 4 flags of its line and an
+// OR over the block's DPP row assembles the 64-bit block mask (bit
+// t = I + 4 J + 16 K).
 #include "geo_internal.h"
 
 namespace {
 
-// spread the 16 bits of x to bit positions 0, 4, 8, ..., 60
-__device__ __forceinline__ unsigned long long spread4(unsigned long long x) {
-    x &= 0xffffull;
-    x = (x | (x << 24)) & 0x000000ff000000ffull;
-    x = (x | (x << 12)) & 0x000f000f000f000full;
-    x = (x | (x << 6)) & 0x0303030303030303ull;
-    x = (x | (x << 3)) & 0x1111111111111111ull;
-    return x;
+// OR of v over the 16 lanes of the wave's row of 16 (DPP row shifts, an
+// inclusive OR-scan): the result is whole in the row's last lane
+__device__ __forceinline__ unsigned row_or16(unsigned v) {
+    v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    return v;
 }
 
 // flags of cells x0..x0+3 of one line from its entries
@@ -74,14 +75,11 @@ __global__ void __launch_bounds__(256) k_voxelize(DevLevel d, const int32_t* off
             const int64_t line = (int64_t)(4 * by + (l & 3)) + (int64_t)ny * (4 * bz + (l >> 2));
             nib = line_nibble(off, val, cap, line, 4 * bx);
         }
-        const unsigned long long b0 = __ballot(nib & 1u), b1 = __ballot(nib & 2u);
-        const unsigned long long b2 = __ballot(nib & 4u), b3 = __ballot(nib & 8u);
-        if (l == 0 && b < d.nblocks) {
-            const int sh = lane;  // 16 * (block slot in the wave)
-            const unsigned long long mask = spread4(b0 >> sh) | (spread4(b1 >> sh) << 1) |
-                                            (spread4(b2 >> sh) << 2) | (spread4(b3 >> sh) << 3);
-            solid[b] = mask;
-        }
+        // the block's 16 lanes are one DPP row: nibble l of the mask comes
+        // from row lane l (bit t = I + 4 J + 16 K with l = J + 4 K)
+        const unsigned lo = row_or16(l < 8 ? nib << (4 * l) : 0u);
+        const unsigned hi = row_or16(l >= 8 ? nib << (4 * (l - 8)) : 0u);
+        if (l == 15 && b < d.nblocks) solid[b] = ((unsigned long long)hi << 32) | lo;
     }
 }
 
