@@ -65,24 +65,41 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_partials(int32_t* partial
     if (threadIdx.x == 0) partials[ntiles] = carry;
 }
 
+// The tile passes through LDS so that global reads and writes are coalesced
+// (lane-consecutive), while each thread scans SCAN_ITEMS consecutive values.
+// The LDS rows are padded by one word per SCAN_ITEMS, so a thread's
+// consecutive items fall in distinct banks.
 __global__ void __launch_bounds__(SCAN_THREADS) k_scan_tiles(const int32_t* in, int32_t* out, int64_t n,
                                                             const int32_t* partials, int64_t ntiles) {
+    __shared__ int tile[SCAN_TILE + SCAN_TILE / SCAN_ITEMS];
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    const int t = threadIdx.x;
+    auto slot = [](int j) { return j + j / SCAN_ITEMS; };
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        const int j = i * SCAN_THREADS + t;
+        tile[slot(j)] = base + j < n ? in[base + j] : 0;
+    }
+    __syncthreads();
     int v[SCAN_ITEMS];
     int s = 0;
 #pragma unroll
     for (int i = 0; i < SCAN_ITEMS; i++) {
-        int64_t k = base + (int64_t)threadIdx.x * SCAN_ITEMS + i;
-        v[i] = k < n ? in[k] : 0;
+        v[i] = tile[slot(t * SCAN_ITEMS + i)];
         s += v[i];
     }
     int tot;
     int ex = block_excl_scan(s, &tot) + partials[blockIdx.x];
 #pragma unroll
     for (int i = 0; i < SCAN_ITEMS; i++) {
-        int64_t k = base + (int64_t)threadIdx.x * SCAN_ITEMS + i;
-        if (k < n) out[k] = ex;
+        tile[slot(t * SCAN_ITEMS + i)] = ex;
         ex += v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        const int j = i * SCAN_THREADS + t;
+        if (base + j < n) out[base + j] = tile[slot(j)];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = partials[ntiles];
 }
