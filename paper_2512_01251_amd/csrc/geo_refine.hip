@@ -1,15 +1,17 @@
 // Refinement flagging of one level (Methodology, "Refinement Flagging and
 // Propagation", Eq. 3), block-parallel (the paper's secondary access mode):
-//   1. 26-neighbour indices through the forest child maps, solid flag;
-//   2. solid-boundary (solid with a fully fluid neighbour) and eligibility
-//      (every in-domain neighbour exists: refining keeps the 2:1 balance);
+//   1-2. 26-neighbour indices through the forest child maps, and in the
+//      same pass the class bits: solid, solid-boundary (solid with a fully
+//      fluid neighbour) and eligibility (every in-domain neighbour exists:
+//      refining keeps the 2:1 balance);
 //   3. marks M1 = (solid-boundary and eligible) or next to a solid-boundary
 //      block; solid-adjacent class for the fluid ones;
 //   4. n_prop synchronous passes (double-buffered, as the paper avoids the
 //      read/write race): fluid blocks, and solid blocks in the first pass,
 //      join when a neighbour is marked;
-//   5. refine = marked and eligible; children emitted in parent order via an
-//      exclusive scan, octant o = ox + 2 oy + 4 oz.
+//   5. refine = marked and eligible (written by the last pass of step 4);
+//      children emitted in parent order via an exclusive scan, octant
+//      o = ox + 2 oy + 4 oz.
 #include "geo_internal.h"
 
 namespace {
@@ -29,17 +31,27 @@ __device__ __forceinline__ void nbr_offset(int k, int& dx, int& dy, int& dz) {
 // first-child indices of those 8 are found by 8 descents of the forest run
 // side by side (their dependent loads overlap), and each neighbour is its
 // parent's first child plus its octant, with no further load.
-__global__ void k_ref_nbr(DevLevel d, const uint64_t* solid, int32_t* nbr, uint8_t* flags) {
+__global__ void k_ref_nbr(DevLevel d, const uint64_t* solid, int32_t* nbr, uint8_t* cls) {
     const int64_t nb = d.nblocks;
     const int L = d.level;
     const int nb0[3] = {d.n0[0] >> 2, d.n0[1] >> 2, d.n0[2] >> 2};
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
         const int bc[3] = {d.bcoord[3 * b], d.bcoord[3 * b + 1], d.bcoord[3 * b + 2]};
+        // class bits from the neighbours' solid words: solid-boundary (solid
+        // with a fully fluid neighbour) and eligible (every in-domain
+        // neighbour exists)
+        bool fluid_nbr = false, elig = true;
+        auto note = [&](int n) {
+            if (n == -1) elig = false;
+            if (n >= 0 && solid[n] == 0ull) fluid_nbr = true;
+        };
         if (L == 0) {  // the dense root grid: no loads
             for (int k = 0; k < 26; k++) {
                 int dx, dy, dz;
                 nbr_offset(k, dx, dy, dz);
-                nbr[(int64_t)k * nb + b] = forest_lookup(d, bc[0] + dx, bc[1] + dy, bc[2] + dz);
+                const int n = forest_lookup(d, bc[0] + dx, bc[1] + dy, bc[2] + dz);
+                nbr[(int64_t)k * nb + b] = n;
+                note(n);
             }
         } else {
             int p0[3];  // lowest parent coordinate per axis (level L-1)
@@ -87,23 +99,12 @@ __global__ void k_ref_nbr(DevLevel d, const uint64_t* solid, int32_t* nbr, uint8
                     r = fc < 0 ? -1 : fc + ((n[0] & 1) | ((n[1] & 1) << 1) | ((n[2] & 1) << 2));
                 }
                 nbr[(int64_t)k * nb + b] = r;
+                note(r);
             }
         }
-        flags[b] = solid[b] != 0ull ? F_S : 0;
-    }
-}
-
-__global__ void k_ref_class(int64_t nb, const int32_t* nbr, const uint8_t* flags, uint8_t* cls) {
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
-        const uint8_t f = flags[b];
-        bool fluid_nbr = false, elig = true;
-        for (int k = 0; k < 26; k++) {
-            const int n = nbr[(int64_t)k * nb + b];
-            if (n == -1) elig = false;  // in-domain neighbour missing: refinement interface
-            if (n >= 0 && !(flags[n] & F_S)) fluid_nbr = true;
-        }
-        uint8_t g = f & F_S;
-        if ((f & F_S) && fluid_nbr) g |= F_SB;
+        const bool is_solid = solid[b] != 0ull;
+        uint8_t g = is_solid ? F_S : 0;
+        if (is_solid && fluid_nbr) g |= F_SB;
         if (elig) g |= F_EL;
         cls[b] = g;
     }
@@ -124,17 +125,25 @@ __global__ void k_ref_m1(int64_t nb, const int32_t* nbr, const uint8_t* flags, u
     }
 }
 
+// one propagation pass; the last one (refine != null) also writes refine =
+// marked and eligible, and its count for the children's scan
 __global__ void k_ref_prop(int64_t nb, const int32_t* nbr, const uint8_t* flags, const uint8_t* Min,
-                           uint8_t* Mout, int first) {
+                           uint8_t* Mout, int first, uint8_t* refine, int32_t* cnt) {
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
         uint8_t m = Min[b];
-        if (!m && (!(flags[b] & F_S) || first)) {
+        const uint8_t f = flags[b];
+        if (!m && (!(f & F_S) || first)) {
             for (int k = 0; k < 26; k++) {
                 const int n = nbr[(int64_t)k * nb + b];
                 if (n >= 0 && Min[n]) { m = 1; break; }
             }
         }
         Mout[b] = m;
+        if (refine) {
+            const int r = (m && (f & F_EL)) ? 1 : 0;
+            refine[b] = (uint8_t)r;
+            cnt[b] = r;
+        }
     }
 }
 
@@ -178,7 +187,7 @@ inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 }  // namespace
 
 size_t geo_refine_ws_bytes(int64_t nb) {
-    return al(sizeof(int32_t) * 26 * (size_t)nb) + 4 * al((size_t)nb) + al(sizeof(int32_t) * (size_t)nb) +
+    return al(sizeof(int32_t) * 26 * (size_t)nb) + 3 * al((size_t)nb) + al(sizeof(int32_t) * (size_t)nb) +
            al(sizeof(int32_t) * ((size_t)nb + 1)) + al(geo_scan_partials_bytes(nb));
 }
 
@@ -190,8 +199,6 @@ int launch_refine(const DevLevel& d, const uint64_t* solid, int n_prop, uint8_t*
     char* p = static_cast<char*>(ws);
     int32_t* nbr = reinterpret_cast<int32_t*>(p);
     p += al(sizeof(int32_t) * 26 * (size_t)nb);
-    uint8_t* flags = reinterpret_cast<uint8_t*>(p);
-    p += al((size_t)nb);
     uint8_t* cls = reinterpret_cast<uint8_t*>(p);
     p += al((size_t)nb);
     uint8_t* M = reinterpret_cast<uint8_t*>(p);
@@ -209,16 +216,17 @@ int launch_refine(const DevLevel& d, const uint64_t* solid, int n_prop, uint8_t*
         return rc;
     }
     const unsigned g = grid_for(nb);
-    k_ref_nbr<<<g, 256, 0, s>>>(d, solid, nbr, flags);
-    k_ref_class<<<g, 256, 0, s>>>(nb, nbr, flags, cls);
+    k_ref_nbr<<<g, 256, 0, s>>>(d, solid, nbr, cls);
     k_ref_m1<<<g, 256, 0, s>>>(nb, nbr, cls, M, bclass);
     for (int k = 1; k <= n_prop; k++) {
-        k_ref_prop<<<g, 256, 0, s>>>(nb, nbr, cls, M, Mn, k == 1 ? 1 : 0);
+        const bool last = k == n_prop;
+        k_ref_prop<<<g, 256, 0, s>>>(nb, nbr, cls, M, Mn, k == 1 ? 1 : 0, last ? refine : nullptr,
+                                     last ? cnt : nullptr);
         uint8_t* t = M;
         M = Mn;
         Mn = t;
     }
-    k_ref_final<<<g, 256, 0, s>>>(nb, cls, M, refine, cnt);
+    if (n_prop == 0) k_ref_final<<<g, 256, 0, s>>>(nb, cls, M, refine, cnt);
     GEO_LAUNCH_CHECK();
     int rc = geo_scan_exclusive(cnt, offs, nb, partials, s);
     if (rc != GEO_OK) return rc;
