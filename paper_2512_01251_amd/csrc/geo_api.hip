@@ -120,8 +120,7 @@ int geo_build_bins(const geo_mesh* mesh, const geo_level* lv, int32_t kind, int3
     const DevMesh m = dev_mesh(mesh);
     const DevLevel d = dev_level(lv);
     int rc;
-    if ((rc = geo_fill_u64(reinterpret_cast<uint64_t*>(out->d_count), 0, 1, s)) != GEO_OK) return rc;
-    if ((rc = geo_fill_i32(cnt, 0, nkeys, s)) != GEO_OK) return rc;
+    if ((rc = geo_zero_counts(reinterpret_cast<uint64_t*>(out->d_count), cnt, nkeys, s)) != GEO_OK) return rc;
     if ((rc = launch_check_mesh(m, d, d_stats, s)) != GEO_OK) return rc;
     if (kind == GEO_BINS_ROWS)
         rc = launch_rows_pass1(m, d, precision, cnt, pairs, rank, out->cap, out->d_count, d_stats, s);
@@ -178,8 +177,7 @@ int geo_build_row_bins_levels(const geo_mesh* mesh, const int32_t n0[3], int32_t
     const DevMesh m = dev_mesh(mesh);
     const DevLevel d = dev_level(&lv);
     int rc;
-    if ((rc = launch_rows_levels_zero(rl, d_pairs, s)) != GEO_OK) return rc;
-    if ((rc = geo_fill_i32(cnt, 0, nkeys, s)) != GEO_OK) return rc;
+    if ((rc = launch_rows_levels_zero(rl, d_pairs, cnt, nkeys, s)) != GEO_OK) return rc;
     if ((rc = launch_check_mesh(m, d, d_stats, s)) != GEO_OK) return rc;
     if ((rc = launch_rows_levels(m, d, precision, rl, cnt, pairs, rank, cap, d_pairs, d_stats, s)) != GEO_OK)
         return rc;

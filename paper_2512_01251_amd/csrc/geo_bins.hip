@@ -526,11 +526,12 @@ __global__ void __launch_bounds__(64) k_rows_levels_f64(DevMesh m, DevLevel d, R
     rows_levels_body<double>(m, d, rl, cnt, pairs, rank, cap, d_pairs, stats);
 }
 
-// zero the per-level counters and the shared pair counter
-__global__ void k_rows_levels_zero(RowLevels rl, int64_t* d_pairs) {
-    const int l = threadIdx.x;
-    if (l < rl.nlev) *rl.count[l] = 0ull;
-    if (l == 0) *d_pairs = 0;
+// zero the per-level counters, the shared pair counter and the key counts
+__global__ void k_rows_levels_zero(RowLevels rl, int64_t* d_pairs, int32_t* cnt, int64_t nkeys) {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i0 < rl.nlev) *rl.count[i0] = 0ull;
+    if (i0 == 0) *d_pairs = 0;
+    for (int64_t i = i0; i < nkeys; i += (int64_t)gridDim.x * blockDim.x) cnt[i] = 0;
 }
 
 // place the pairs of every level: the level of a pair is found from its key
@@ -809,8 +810,8 @@ int launch_rows_levels(const DevMesh& m, const DevLevel& d, int precision, const
     return GEO_OK;
 }
 
-int launch_rows_levels_zero(const RowLevels& rl, int64_t* d_pairs, hipStream_t s) {
-    k_rows_levels_zero<<<1, 64, 0, s>>>(rl, d_pairs);
+int launch_rows_levels_zero(const RowLevels& rl, int64_t* d_pairs, int32_t* cnt, int64_t nkeys, hipStream_t s) {
+    k_rows_levels_zero<<<grid_for(nkeys, 256, 16384), 256, 0, s>>>(rl, d_pairs, cnt, nkeys);
     GEO_LAUNCH_CHECK();
     return GEO_OK;
 }

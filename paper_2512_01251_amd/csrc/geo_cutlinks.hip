@@ -170,8 +170,10 @@ __device__ __forceinline__ void block_link_mask2(const DevLevel& d, const int32_
 
 __global__ void __launch_bounds__(64) k_cl_mask(DevLevel d, const int32_t* off, const int32_t* val, int64_t cap,
                                                 const int32_t* loff, int lattice, uint32_t* wmask, int zero_fill,
-                                                int32_t* blk_cnt) {
+                                                int32_t* blk_cnt, int32_t* fixn) {
     __shared__ unsigned halo[72];
+    // the exact pass's queue counters start at zero (read from the next launch on)
+    if (blockIdx.x == 0 && threadIdx.x < 3) fixn[threadIdx.x] = 0;
     const uint32_t dirs = lattice_dirs(lattice);
     const int lane = threadIdx.x;
     const int64_t nchunks = (d.nblocks + 63) / 64;
@@ -1252,13 +1254,12 @@ int launch_cutlinks(const DevMesh& m, const DevLevel& d, const geo_bins* rows, c
     const int64_t nchunk = (nb + 63) / 64;
     const unsigned g = (unsigned)(nchunk < 32768 ? nchunk : 32768);
     k_cl_mask<<<g, 64, 0, s>>>(d, rows->off, rows->val, rows->cap, links->off, lattice, wmask, link_mask ? 1 : 0,
-                               blk_cnt);
+                               blk_cnt, fixn);
     GEO_LAUNCH_CHECK();
     // exact link count (the table's offsets are int32)
     int rc = geo_sum_i32(blk_cnt, nb, d_nlinks, s);
     if (rc != GEO_OK) return rc;
     if ((rc = geo_scan_exclusive(blk_cnt, blk_off, nb, partials, s)) != GEO_OK) return rc;
-    if ((rc = geo_fill_i32(fixn, 0, 3, s)) != GEO_OK) return rc;
     const unsigned gb = (unsigned)((nb + 255) / 256 < 65536 ? (nb + 255) / 256 : 65536);
     k_cl_ntask<<<gb, 256, 0, s>>>(nb, blk_off, links->off, links->cap, ntask, mlist, mcount);
     GEO_LAUNCH_CHECK();

@@ -281,6 +281,8 @@ __device__ __forceinline__ void wave_count(uint64_t* ctr, unsigned n) {
 // kernel timer is on for that kernel (no-op otherwise)
 void kt_record(int kernel, hipStream_t s, bool stop);
 
+// zero *one and p[0..n-1] (one launch)
+int geo_zero_counts(uint64_t* one, int32_t* p, int64_t n, hipStream_t s);
 int geo_scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* partials,
                        hipStream_t s);
 size_t geo_scan_partials_bytes(int64_t n);
@@ -301,7 +303,7 @@ struct RowLevels {
 };
 int launch_rows_levels(const DevMesh& m, const DevLevel& d, int precision, const RowLevels& rl, int32_t* cnt,
                        int2* pairs, int32_t* rank, int64_t cap, int64_t* d_pairs, uint64_t* d_stats, hipStream_t s);
-int launch_rows_levels_zero(const RowLevels& rl, int64_t* d_pairs, hipStream_t s);
+int launch_rows_levels_zero(const RowLevels& rl, int64_t* d_pairs, int32_t* cnt, int64_t nkeys, hipStream_t s);
 int launch_rows_levels_scatter(const int2* pairs, const int32_t* rank, int64_t cap, const int64_t* d_pairs,
                                const RowLevels& rl, hipStream_t s);
 int launch_rows_pass1(const DevMesh& m, const DevLevel& d, int precision, int32_t* cnt,

@@ -109,6 +109,13 @@ __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
         p[i] = v;
 }
 
+// zero one 64-bit counter and n 32-bit counts in one launch
+__global__ void k_zero_counts(uint64_t* one, int32_t* p, int64_t n) {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i0 == 0) *one = 0ull;
+    for (int64_t i = i0; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
 __global__ void k_fill_u64(uint64_t* p, uint64_t v, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -163,6 +170,12 @@ int geo_scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* part
 int geo_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
     if (n <= 0) return GEO_OK;
     k_fill_i32<<<grid_for(n, 256), 256, 0, s>>>(p, v, n);
+    GEO_LAUNCH_CHECK();
+    return GEO_OK;
+}
+
+int geo_zero_counts(uint64_t* one, int32_t* p, int64_t n, hipStream_t s) {
+    k_zero_counts<<<grid_for(n > 0 ? n : 1, 256), 256, 0, s>>>(one, p, n);
     GEO_LAUNCH_CHECK();
     return GEO_OK;
 }
