@@ -258,8 +258,8 @@ __device__ __forceinline__ void tri_load(const DevMesh& m, int64_t t, TriLoad& t
 
 // Set up the local frame of level L.  Returns false for triangles with no line.
 template <typename R>
-__device__ bool row_setup(const TriLoad& tl, int L, int ny, int nz, RowTri<R>& T, int& jlo, int& jhi,
-                          int& klo, int& khi) {
+__device__ bool row_setup(const TriLoad& tl, int L, int ny, int nz, bool f32_verts, RowTri<R>& T, int& jlo,
+                          int& jhi, int& klo, int& khi) {
     const double s = ldexp(1.0, L);
     const int(&id)[3] = tl.id;
     double X[3][3];  // the same float64 operations as scaled64
@@ -273,9 +273,11 @@ __device__ bool row_setup(const TriLoad& tl, int L, int ny, int nz, RowTri<R>& T
     khi = (int)fmin(floor(zmax), (double)(nz - 1));
     if (jlo > jhi || klo > khi) return false;
     // origin: x from vertex 0, y/z from the first line; fall back to 0 on an
-    // axis where the translation would not be exact in float64
+    // axis where the translation would not be exact in float64.  Float32
+    // vertices within the coordinate contract (0 or [1/4, n0], n0 2^L <=
+    // 2^15) need no check: X and X - o span at most 2^14 .. 2^-25, 40 bits.
     int o[3] = {(int)floor(X[0][0]), jlo, klo};
-    for (int a = 0; a < 3; a++) {
+    for (int a = 0; a < 3 && !f32_verts; a++) {
         bool exact = true;
         for (int i = 0; i < 3; i++) {
             // Knuth's two-sum error of X - o: zero iff the difference is exact
@@ -423,7 +425,7 @@ __device__ __forceinline__ int rows_level(const DevMesh& m, bool live, const Tri
     RowTri<R> T;
     int jlo = 0, jhi = -1, klo = 0, khi = -1;
     int mode = 0, drop = 0, areaSign = 0;
-    if (live && row_setup<R>(tl, L, ny, nz, T, jlo, jhi, klo, khi)) {
+    if (live && row_setup<R>(tl, L, ny, nz, m.vdtype == GEO_F32, T, jlo, jhi, klo, khi)) {
         const int ayz = chain_area<R>(m, T, s, 1, 2, st);
         if (ayz < 0) swap_bc<R>(T);
         if (ayz != 0) {
