@@ -279,6 +279,6 @@ int geo_solid_change(int64_t nblocks, const uint64_t* prev, const uint64_t* cur,
                                (hipStream_t)stream);
 }
 
-const char* geo_version(void) { return "libgeo 0.1 (gfx950)"; }
+const char* geo_version(void) { return "libgeo 0.2 (gfx950)"; }
 
 }  // extern "C"
