@@ -67,12 +67,15 @@ class Embedding:
 
 
 class Embedder:
-    """Holds the workspace and remembered capacities across calls."""
+    """Holds the workspace and remembered capacities across calls.  The
+    level-0 block list of a grid is built once and shared, read-only, by the
+    embeddings it returns for that grid."""
 
     def __init__(self, device="cuda"):
         self.device = torch.device(device)
         self.ws = torch.empty(0, dtype=torch.uint8, device=self.device)
         self.caps: dict = {}                 # remembered buffer capacities
+        self._level0: dict = {}              # level-0 block list of the last grid
         # pinned host word for the per-level block count (read without a
         # stream-wide wait)
         self._host_n = torch.zeros(1, dtype=torch.int64, pin_memory=self.device.type == "cuda")
@@ -141,8 +144,14 @@ class Embedder:
         cnt = lambda i: ctr[GEO_NSTATS + i:GEO_NSTATS + i + 1]
         checks = []   # (counter index, capacity, capacity key, apply(count))
         nb0 = (n0[0] // 4) * (n0[1] // 4) * (n0[2] // 4)
-        bcoord = torch.empty((nb0, 3), dtype=torch.int32, device=dev)
-        geo_level0_blocks(n0, bcoord)
+        # the level-0 blocks depend on n0 only: built once per grid and shared
+        # (read-only) by the embeddings of later calls
+        key0 = ("level0", tuple(int(x) for x in n0))
+        bcoord = self._level0.get(key0)
+        if bcoord is None:
+            bcoord = torch.empty((nb0, 3), dtype=torch.int32, device=dev)
+            geo_level0_blocks(n0, bcoord)
+            self._level0 = {key0: bcoord}
         out = Embedding(tuple(n0), lf, lattice)
         child_maps = []
         rows = None
