@@ -19,11 +19,10 @@ from dataclasses import dataclass, field
 import torch
 
 from . import (GEO_BINS_LINKS, GEO_BINS_ROWS, GEO_CALL_BINS_LINKS, GEO_CALL_BINS_ROWS, GEO_CALL_BINS_ROWS_LEVELS,
-               GEO_CALL_CUTLINKS,
-               GEO_CALL_LINKS_DENSE, GEO_CALL_REFINE, GEO_NSTATS, GEO_STAT_CONTRACT, GEO_PREC_F32_FALLBACK, GEO_PREC_F64,
-               geo_build_bins, geo_build_row_bins_levels, geo_cutlinks, geo_cutlinks_backward, geo_level0_blocks, geo_links_dense, geo_nprop,
-               geo_refine_flags, geo_solid_change, geo_voxelize, geo_workspace_size, make_bins, make_level,
-               make_mesh)
+               GEO_CALL_CUTLINKS, GEO_CALL_LINKS_DENSE, GEO_CALL_REFINE, GEO_NSTATS, GEO_STAT_CONTRACT,
+               GEO_PREC_F32_FALLBACK, GEO_PREC_F64, geo_bins, geo_build_bins, geo_build_row_bins_levels, geo_cutlinks,
+               geo_cutlinks_backward, geo_level0_blocks, geo_links_dense, geo_nprop, geo_refine_flags,
+               geo_solid_change, geo_voxelize, geo_workspace_size, make_bins, make_level, make_mesh)
 
 PRECISIONS = {"f64": GEO_PREC_F64, "f32": GEO_PREC_F32_FALLBACK}
 POLL_S = 0.05   # longest poll of a pinned count before the event's wait takes over
@@ -239,14 +238,17 @@ class Embedder:
             pos = (pos + max(cap, 1) + 63) // 64 * 64
             spans.append((nkeys, key, cap, o, v))
         buf = torch.empty(pos, dtype=torch.int32, device=dev)
+        # descriptors from addresses, so that the launch does not wait for the
+        # tensor views (made while the GPU runs the pass)
+        base, cbase = buf.data_ptr(), cnt(0).data_ptr()
         for L, (nkeys, key, cap, o, v) in enumerate(spans):
-            off, val = buf[o:o + nkeys + 1], buf[v:v + max(cap, 1)]
-            bins.append(make_bins(GEO_BINS_ROWS, nkeys, off, val, cap, cnt(L)))
-            out.append((nkeys, key, cap, off, val, bins[-1]))
-        ws = self._workspace(geo_workspace_size(GEO_CALL_BINS_ROWS_LEVELS, sum(o[0] for o in out),
-                                                sum(o[2] for o in out)))
+            bins.append(geo_bins(GEO_BINS_ROWS, nkeys, base + 4 * o, base + 4 * v, cap, cbase + 8 * L))
+        ws = self._workspace(geo_workspace_size(GEO_CALL_BINS_ROWS_LEVELS, sum(x[0] for x in spans),
+                                                sum(x[2] for x in spans)))
         with self._timed("rows"):
             geo_build_row_bins_levels(mesh, n0, 0, prec, bins, stats, ws)
+        for L, (nkeys, key, cap, o, v) in enumerate(spans):
+            out.append((nkeys, key, cap, buf[o:o + nkeys + 1], buf[v:v + max(cap, 1)], bins[L]))
         return out
 
     def _bins(self, mesh, lvd, kind, prec, nkeys, stats, cap, d_count, tname):
