@@ -269,7 +269,9 @@ class Embedder:
         nb = lvd.nblocks
         key = ("links", lf)
         bcap = self.caps.get(key, max(4096, 8 * mesh.nt))
-        loff, lval = self._bins(mesh, lvd, GEO_BINS_LINKS, prec, nb, stats, bcap, d_bins, "linkbins")
+        # no statistics: the vertex contract was counted by the ROWS call, and
+        # the LINKS pass keeps no other counter
+        loff, lval = self._bins(mesh, lvd, GEO_BINS_LINKS, prec, nb, None, bcap, d_bins, "linkbins")
         links = make_bins(GEO_BINS_LINKS, nb, loff, lval, bcap, d_bins)
         mask = torch.empty(nb * 64, dtype=torch.int32, device=dev) if with_mask else None
         lkey = ("links_table", lf)
